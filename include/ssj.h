@@ -1,0 +1,186 @@
+/*
+ * ssj.h -- exact set similarity join with the Bitmap Filter on one AMD
+ * Instinct MI355X (gfx950).  C ABI, version 1.
+ *
+ * Method: Sandes, Teodoro, Melo, "Bitmap Filter: Speeding up Exact Set
+ * Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
+ *
+ * The problem (Section 2.1, Eq. 1): given collections R and S of token
+ * sets, return every pair (r, s) in R x S with sim(r, s) >= t; when R and
+ * S are the same collection this is the self-join.  The threshold is an
+ * exact rational t = p / q and every comparison is done in integers, so
+ * pairs exactly on the threshold are decided exactly and the pair set is
+ * unique: it does not depend on the bitmap width, the bitmap generator,
+ * the tiling or the launch shape.
+ *
+ * Conventions shared by every entry point:
+ *   - A collection (ssj_sets) is CSR in DEVICE memory: set k is
+ *     tokens[offsets[k] .. offsets[k+1]).  offsets[0] must be 0, offsets
+ *     must be non-decreasing and offsets[n_sets] must equal n_tokens;
+ *     otherwise SSJ_E_INVALID.  Every set must be strictly increasing
+ *     (sorted, no repeated token); otherwise SSJ_E_UNSORTED.  Empty sets
+ *     are legal and never pair with anything.  n_sets < 2^32 - 1.
+ *   - Input buffers are caller-owned; the library never frees them and
+ *     only reads them.
+ *   - Bitmaps are b bits per set, b a multiple of 64 in [64, 4096], stored
+ *     as b/64 uint64 words per set, set k at words [k*b/64, (k+1)*b/64),
+ *     caller order.  Bit k of a bitmap is bit (k % 64) of word k / 64.
+ *     The hash is h(t) = t mod b (Section 5.1).
+ *   - All device work is enqueued on hip_stream (a hipStream_t; NULL is
+ *     the default stream).  A join returns after that stream has been
+ *     synchronised, because the number of pairs must be known.
+ *   - Result pairs are returned in HOST memory owned by the library
+ *     (ssj_pairs.pairs), released with ssj_free_pairs.  On any error
+ *     *out is {NULL, 0}: there is never a partial result.
+ *   - Calls are re-entrant; calls on distinct streams are independent.
+ *     The library allocates its working memory per call.
+ *   - Return values are ssj_status codes; 0 is success.
+ */
+#ifndef SSJ_H
+#define SSJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSJ_ABI_VERSION 1
+
+typedef enum {
+  SSJ_OK = 0,
+  SSJ_E_INVALID = -1,     /* bad argument or malformed offsets */
+  SSJ_E_UNSORTED = -2,    /* a set is not strictly increasing */
+  SSJ_E_NOMEM = -3,       /* a device or host allocation failed */
+  SSJ_E_DEVICE = -4,      /* a HIP runtime call or kernel launch failed */
+  SSJ_E_UNSUPPORTED = -5  /* similarity function or generator not available */
+} ssj_status;
+
+/* Similarity functions of Table 1.  Jaccard |r n s| / |r u s| is the one
+ * the paper's GPU algorithm (Alg. 8) evaluates. */
+typedef enum {
+  SSJ_SIM_JACCARD = 0,
+  SSJ_SIM_DICE = 1,
+  SSJ_SIM_COSINE = 2,
+  SSJ_SIM_OVERLAP = 3
+} ssj_sim;
+
+/* Bitmap generators of Section 3.2: Bitmap-Xor (Alg. 4), Bitmap-Set
+ * (Alg. 3), Bitmap-Next (Alg. 5).  Theorem 1 holds for all three; the
+ * join treats any of them alike. */
+typedef enum {
+  SSJ_BM_XOR = 0,
+  SSJ_BM_SET = 1,
+  SSJ_BM_NEXT = 2
+} ssj_bm_method;
+
+typedef struct {
+  const uint64_t *offsets; /* device, n_sets + 1 entries */
+  const uint32_t *tokens;  /* device, n_tokens entries */
+  uint64_t n_sets;
+  uint64_t n_tokens;
+} ssj_sets;
+
+typedef struct {
+  uint32_t i, j;
+} ssj_pair;
+
+typedef struct {
+  ssj_pair *pairs; /* host, library-owned; NULL when count == 0 */
+  uint64_t count;
+} ssj_pairs;
+
+/* Optional per-call statistics. */
+typedef struct {
+  uint64_t band_pairs;      /* pairs inside the length band (Table 2) */
+  uint64_t survivors;       /* band pairs the bitmap filter kept */
+  uint64_t results;         /* pairs reported */
+  uint32_t filter_launches; /* filter kernel launches (1 + queue drains) */
+  uint32_t b_bits;          /* bitmap width used */
+  float ms_total;           /* call entry to pairs in host memory */
+  float ms_prepare;         /* validation, size sort, plan, bitmaps */
+  float ms_filter;          /* sum of filter kernel durations */
+  float ms_verify;          /* sum of verification kernel durations */
+  float ms_emit;            /* result sort and copy to the host */
+} ssj_stats;
+
+/* Optional knobs; pass NULL for the defaults. */
+typedef struct {
+  uint64_t queue_capacity; /* survivor-queue entries per drain; 0 = default;
+                              raised to at least 4096 */
+  uint32_t tile_cols;      /* columns per filter tile; 0 = default */
+  uint32_t flags;          /* SSJ_FLAG_* */
+} ssj_options;
+
+/* Report every survivor of the bitmap filter as a result, skipping the
+ * exact verification.  Diagnostic only: the output is then the filter's
+ * survivor set (caller indices), not the join. */
+#define SSJ_FLAG_SURVIVORS_ONLY 1u
+
+/*
+ * ssj_build_bitmaps -- the bitmap of every set (Section 3.2, Alg. 3/4/5,
+ * precomputed once as in the initialization of Alg. 7).
+ *   s            collection (device CSR), validated as above
+ *   b_bits       bitmap width b: multiple of 64 in [64, 4096]
+ *   method       ssj_bm_method
+ *   bitmaps_dev  caller-owned device buffer of n_sets * b_bits / 64 uint64,
+ *                written in caller order
+ *   hip_stream   stream for the work; the call returns after the stream
+ *                is synchronised (validation result is needed)
+ * Errors: SSJ_E_INVALID (null pointer, bad b, bad offsets),
+ *         SSJ_E_UNSORTED, SSJ_E_UNSUPPORTED (unknown method),
+ *         SSJ_E_NOMEM, SSJ_E_DEVICE.
+ */
+int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *bitmaps_dev,
+                      void *hip_stream);
+
+/*
+ * ssj_self_join -- every pair (i, j), i < j (caller indices), with
+ * sim(set_i, set_j) >= p / q (Eq. 1 with R = S).  The length filter
+ * (Table 2) bounds the pairs considered, the bitmap filter (Theorem 1,
+ * Eq. 2; Alg. 7 without the cutoff) prunes them, and every survivor is
+ * verified exactly.
+ *   s            collection (device CSR)
+ *   bitmaps_dev  NULL: Bitmap-Xor bitmaps of width b_bits are built
+ *                internally.  Otherwise caller-owned device bitmaps of
+ *                width b_bits from any generator (caller order).
+ *   b_bits       bitmap width: multiple of 64 in [64, 4096]
+ *   sim          ssj_sim; only SSJ_SIM_JACCARD is available (others
+ *                return SSJ_E_UNSUPPORTED)
+ *   p, q         threshold t = p / q, 1 <= p <= q (reduced internally)
+ *   opts         NULL or knobs
+ *   out          receives the pairs, ascending by (i, j), no duplicates
+ *   stats        NULL or statistics
+ *   hip_stream   stream for all device work
+ * Errors: SSJ_E_INVALID, SSJ_E_UNSORTED, SSJ_E_UNSUPPORTED, SSJ_E_NOMEM,
+ *         SSJ_E_DEVICE; *out = {NULL, 0} on every error.
+ */
+int ssj_self_join(const ssj_sets *s, const uint64_t *bitmaps_dev, uint32_t b_bits, int sim,
+                  uint32_t p, uint32_t q, const ssj_options *opts, ssj_pairs *out,
+                  ssj_stats *stats, void *hip_stream);
+
+/*
+ * ssj_rs_join -- every pair (i in R, j in S) with sim(r_i, s_j) >= p / q
+ * (Eq. 1, R-S join).  Arguments as ssj_self_join; the bitmaps of R and S,
+ * when given, must come from the same generator and width (the bound of
+ * Theorem 1 needs the same hash on both sides).  Output ascending by
+ * (i, j).
+ */
+int ssj_rs_join(const ssj_sets *r, const uint64_t *r_bitmaps_dev, const ssj_sets *s,
+                const uint64_t *s_bitmaps_dev, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
+                const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream);
+
+/* Release the pairs of a join.  NULL-safe and idempotent; zeroes *out. */
+void ssj_free_pairs(ssj_pairs *out);
+
+/* Static text for a status code. */
+const char *ssj_status_string(int status);
+
+/* SSJ_ABI_VERSION of the loaded library. */
+int ssj_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSJ_H */

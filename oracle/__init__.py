@@ -67,6 +67,8 @@ def _load():
         lib.oracle_survivors.argtypes = [vp, u64, vp, ctypes.c_uint32, vp, u64, u64, c_int, vp,
                                          ctypes.POINTER(_u64p)]
         lib.oracle_survivors.restype = i64
+        lib.oracle_check_pairs.argtypes = [vp, vp, vp, vp, vp, u64, c_int, u64, u64, vp]
+        lib.oracle_check_pairs.restype = None
         lib.oracle_free.argtypes = [vp]
         lib.oracle_free.restype = None
         _lib = lib
@@ -256,3 +258,16 @@ def survivors(offsets, bms, b: int, p: int, q: int, order=None, listing: bool = 
         raise MemoryError("oracle failed")
     pairs = _take_pairs(ptr, int(cnt)) if listing else None
     return int(cnt), int(band.value), pairs
+
+
+def check_pairs(r_offsets, r_tokens, s_offsets, s_tokens, pairs, p: int, q: int,
+                sim: int = JACCARD) -> np.ndarray:
+    """Boolean array: sim >= p/q for each (i, j) row of ``pairs`` (R x S)."""
+    lib = _load()
+    ro, rt, so, st = _u64(r_offsets), _u32(r_tokens), _u64(s_offsets), _u32(s_tokens)
+    pr = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    ok = np.zeros(max(len(pr), 1), dtype=np.uint8)
+    pb = pr if pr.size else np.zeros((1, 2), dtype=np.uint32)
+    lib.oracle_check_pairs(ro.ctypes.data, rt.ctypes.data, so.ctypes.data, st.ctypes.data,
+                           pb.ctypes.data, len(pr), sim, p, q, ok.ctypes.data)
+    return ok[:len(pr)].astype(bool)

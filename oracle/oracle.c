@@ -468,4 +468,18 @@ int64_t oracle_survivors(const uint64_t *offsets, uint64_t n, const uint64_t *bi
   return rc;
 }
 
+/* For each listed pair (i, j) of collections R and S: 1 when sim >= p/q
+ * (Table 1 by merge), else 0.  Used to re-verify pairs reported at sizes the
+ * full oracle cannot enumerate. */
+void oracle_check_pairs(const uint64_t *r_off, const uint32_t *r_tok, const uint64_t *s_off,
+                        const uint32_t *s_tok, const uint32_t *pairs, uint64_t n_pairs, int sim,
+                        uint64_t p, uint64_t q, uint8_t *ok_out) {
+  for (uint64_t k = 0; k < n_pairs; ++k) {
+    uint64_t i = pairs[2 * k], j = pairs[2 * k + 1];
+    uint64_t ni = set_len(r_off, i), nj = set_len(s_off, j), o, u;
+    oracle_merge_count(r_tok + r_off[i], ni, s_tok + s_off[j], nj, &o, &u);
+    ok_out[k] = (uint8_t)(u != 0 && oracle_similar(sim, o, u, ni, nj, p, q));
+  }
+}
+
 void oracle_free(void *p) { free(p); }

@@ -1,0 +1,213 @@
+"""Exact set similarity join with the Bitmap Filter on AMD Instinct MI355X.
+
+Python binding of ``libssj.so`` (the C ABI declared in ``include/ssj.h``).
+This module only marshals arguments: every step of a join runs in the
+library's HIP kernels.  PyTorch provides device memory and streams.
+
+Method: Sandes, Teodoro, Melo, "Bitmap Filter: Speeding up Exact Set
+Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssj.so")
+
+SSJ_OK, SSJ_E_INVALID, SSJ_E_UNSORTED, SSJ_E_NOMEM, SSJ_E_DEVICE, SSJ_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+SSJ_SIM_JACCARD, SSJ_SIM_DICE, SSJ_SIM_COSINE, SSJ_SIM_OVERLAP = 0, 1, 2, 3
+SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT = 0, 1, 2
+SSJ_FLAG_SURVIVORS_ONLY = 1
+
+EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_free_pairs",
+           "ssj_status_string", "ssj_abi_version")
+
+
+class ssj_sets(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("tokens", ctypes.c_void_p),
+                ("n_sets", ctypes.c_uint64), ("n_tokens", ctypes.c_uint64)]
+
+
+class ssj_pair(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32)]
+
+
+class ssj_pairs(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.POINTER(ssj_pair)), ("count", ctypes.c_uint64)]
+
+
+class ssj_stats(ctypes.Structure):
+    _fields_ = [("band_pairs", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
+                ("results", ctypes.c_uint64), ("filter_launches", ctypes.c_uint32),
+                ("b_bits", ctypes.c_uint32), ("ms_total", ctypes.c_float),
+                ("ms_prepare", ctypes.c_float), ("ms_filter", ctypes.c_float),
+                ("ms_verify", ctypes.c_float), ("ms_emit", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ssj_options(ctypes.Structure):
+    _fields_ = [("queue_capacity", ctypes.c_uint64), ("tile_cols", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class SsjError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The built library.  Raises when it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1711_07295_amd/build.py`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, c_int = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        sp = ctypes.POINTER(ssj_sets)
+        lib.ssj_build_bitmaps.argtypes = [sp, u32, c_int, vp, vp]
+        lib.ssj_build_bitmaps.restype = c_int
+        lib.ssj_self_join.argtypes = [sp, vp, u32, c_int, u32, u32, ctypes.POINTER(ssj_options),
+                                      ctypes.POINTER(ssj_pairs), ctypes.POINTER(ssj_stats), vp]
+        lib.ssj_self_join.restype = c_int
+        lib.ssj_rs_join.argtypes = [sp, vp, sp, vp, u32, c_int, u32, u32,
+                                    ctypes.POINTER(ssj_options), ctypes.POINTER(ssj_pairs),
+                                    ctypes.POINTER(ssj_stats), vp]
+        lib.ssj_rs_join.restype = c_int
+        lib.ssj_free_pairs.argtypes = [ctypes.POINTER(ssj_pairs)]
+        lib.ssj_free_pairs.restype = None
+        lib.ssj_status_string.argtypes = [c_int]
+        lib.ssj_status_string.restype = ctypes.c_char_p
+        lib.ssj_abi_version.argtypes = []
+        lib.ssj_abi_version.restype = c_int
+        _lib = lib
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return load().ssj_status_string(status).decode()
+
+
+def ssj_abi_version() -> int:
+    return load().ssj_abi_version()
+
+
+@dataclass
+class DeviceSets:
+    """A collection in device memory (CSR), kept alive with its tensors."""
+    offsets: object  # torch uint64 tensor [N+1] on the GPU
+    tokens: object   # torch int32/uint32 tensor [T] on the GPU
+
+    @property
+    def n_sets(self) -> int:
+        return int(self.offsets.numel()) - 1
+
+    @property
+    def n_tokens(self) -> int:
+        return int(self.tokens.numel())
+
+    def c(self) -> ssj_sets:
+        return ssj_sets(self.offsets.data_ptr() if self.offsets.numel() else None,
+                        self.tokens.data_ptr() if self.tokens.numel() else None,
+                        self.n_sets, self.n_tokens)
+
+
+def to_device(offsets, tokens, device="cuda") -> DeviceSets:
+    """Upload a host CSR collection (uint64 offsets, uint32 tokens)."""
+    import torch
+    off = np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)
+    tok = np.ascontiguousarray(tokens, dtype=np.uint32).view(np.int32)
+    return DeviceSets(torch.from_numpy(off.copy()).to(device),
+                      torch.from_numpy(tok.copy()).to(device))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _take(out: ssj_pairs) -> np.ndarray:
+    n = int(out.count)
+    try:
+        if n == 0:
+            return np.zeros((0, 2), dtype=np.uint32)
+        raw = np.ctypeslib.as_array(ctypes.cast(out.pairs, ctypes.POINTER(ctypes.c_uint32)),
+                                    shape=(n * 2,))
+        return raw.reshape(n, 2).copy()
+    finally:
+        load().ssj_free_pairs(ctypes.byref(out))
+
+
+def _opts(queue_capacity=0, tile_cols=0, flags=0):
+    if not (queue_capacity or tile_cols or flags):
+        return None
+    return ssj_options(queue_capacity, tile_cols, flags)
+
+
+def ssj_build_bitmaps(sets: DeviceSets, b_bits: int, method: int = SSJ_BM_XOR, out=None,
+                      stream=None):
+    """Bitmaps of every set (caller order) as a (N, b/64) int64 tensor."""
+    import torch
+    if out is None:
+        out = torch.empty((sets.n_sets, b_bits // 64), dtype=torch.int64,
+                          device=sets.offsets.device)
+    cs = sets.c()
+    st = load().ssj_build_bitmaps(ctypes.byref(cs), b_bits, method,
+                                  out.data_ptr() if out.numel() else None, _stream(stream))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_build_bitmaps")
+    return out
+
+
+def ssj_self_join(sets: DeviceSets, p: int, q: int, b_bits: int = 64, bitmaps=None,
+                  sim: int = SSJ_SIM_JACCARD, queue_capacity: int = 0, tile_cols: int = 0,
+                  flags: int = 0, stream=None):
+    """All pairs (i, j), i < j, with sim >= p/q.  Returns ((n, 2) uint32 array, stats dict)."""
+    cs = sets.c()
+    out, stats = ssj_pairs(), ssj_stats()
+    o = _opts(queue_capacity, tile_cols, flags)
+    st = load().ssj_self_join(ctypes.byref(cs), _ptr(bitmaps), b_bits, sim, p, q,
+                              ctypes.byref(o) if o else None, ctypes.byref(out),
+                              ctypes.byref(stats), _stream(stream))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_self_join")
+    return _take(out), stats.as_dict()
+
+
+def ssj_rs_join(r: DeviceSets, s: DeviceSets, p: int, q: int, b_bits: int = 64, r_bitmaps=None,
+                s_bitmaps=None, sim: int = SSJ_SIM_JACCARD, queue_capacity: int = 0,
+                tile_cols: int = 0, flags: int = 0, stream=None):
+    """All pairs (i in R, j in S) with sim >= p/q.  Returns (pairs, stats dict)."""
+    cr, cs = r.c(), s.c()
+    out, stats = ssj_pairs(), ssj_stats()
+    o = _opts(queue_capacity, tile_cols, flags)
+    st = load().ssj_rs_join(ctypes.byref(cr), _ptr(r_bitmaps), ctypes.byref(cs),
+                            _ptr(s_bitmaps), b_bits, sim, p, q, ctypes.byref(o) if o else None,
+                            ctypes.byref(out), ctypes.byref(stats), _stream(stream))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_rs_join")
+    return _take(out), stats.as_dict()
+
+
+def ssj_free_pairs(out: ssj_pairs) -> None:
+    load().ssj_free_pairs(ctypes.byref(out))

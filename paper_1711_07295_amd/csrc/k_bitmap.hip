@@ -1,0 +1,155 @@
+// Bitmap generation (Section 3.2) and the strict-order check of the input
+// sets.  The hash is h(t) = t mod b (Section 5.1); bit k of a bitmap is bit
+// k % 64 of 64-bit word k / 64.
+//
+//   Bitmap-Xor (Alg. 4): flip bit h(t) for every token -- bit k ends set iff
+//     an odd number of tokens hash to k.  The join's default.
+//   Bitmap-Set (Alg. 3): set bit h(t) for every token.
+//   Bitmap-Next (Alg. 5): all ones when n >= b; otherwise each token takes
+//     bit h(t) or the next free bit after it, cyclically.  The occupied
+//     bits do not depend on the order the tokens are taken in.
+//
+// One wave per set: lanes stride over the set's tokens (coalesced reads of
+// the CSR token array), combine their bits in a per-wave LDS bitmap with
+// LDS atomics, and lane w writes word w.  The kernel is bound by HBM reads
+// of the tokens (4 bytes per token) and writes of b/8 bytes per set.
+#include "ssj_internal.h"
+
+namespace ssj {
+namespace {
+
+constexpr int kWavesPerBlock = kBlock / 64;
+
+template <int METHOD, bool POW2>
+__global__ __launch_bounds__(kBlock) void k_build_bitmaps(
+    const uint64_t *__restrict__ offsets, const uint32_t *__restrict__ tokens,
+    const uint32_t *__restrict__ perm, uint64_t n, uint32_t b_bits, uint32_t out_words,
+    uint64_t *__restrict__ out, JoinCounters *__restrict__ ctr) {
+  __shared__ uint32_t lbits[kWavesPerBlock][2 * kMaxWords];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const uint64_t x = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+  if (x >= n) return;  // whole wave leaves together
+  uint32_t *bits = lbits[w];
+  for (uint32_t i = lane; i < 2 * out_words; i += 64) bits[i] = 0;
+  const uint64_t k = perm ? perm[x] : x;
+  if (k >= n) return;
+  const uint64_t o0 = offsets[k], o1 = offsets[k + 1];
+  const uint32_t nt = (uint32_t)(o1 - o0);
+  const uint32_t mask = b_bits - 1;
+  bool unsorted = false;
+  if (METHOD == SSJ_BM_NEXT) {
+    // Alg. 5: saturated when n >= b, else linear probing by one lane.
+    for (uint64_t t = o0 + lane; t + 1 < o1; t += 64)
+      unsorted |= !(tokens[t] < tokens[t + 1]);
+    if (nt >= b_bits) {
+      for (uint32_t i = lane; i < 2 * (b_bits / 64); i += 64) bits[i] = 0xFFFFFFFFu;
+    } else if (lane == 0) {
+      for (uint64_t t = o0; t < o1; ++t) {
+        uint32_t v = tokens[t];
+        uint32_t s = POW2 ? (v & mask) : (v % b_bits);
+        while ((bits[s >> 5] >> (s & 31)) & 1u) s = (s + 1 == b_bits) ? 0 : s + 1;
+        bits[s >> 5] |= 1u << (s & 31);
+      }
+    }
+  } else {
+    for (uint64_t t = o0 + lane; t < o1; t += 64) {
+      uint32_t v = tokens[t];
+      if (t + 1 < o1) unsorted |= !(v < tokens[t + 1]);
+      uint32_t s = POW2 ? (v & mask) : (v % b_bits);
+      if (METHOD == SSJ_BM_XOR) atomicXor(&bits[s >> 5], 1u << (s & 31));
+      else atomicOr(&bits[s >> 5], 1u << (s & 31));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  uint64_t *dst = out + x * out_words;
+  for (uint32_t i = lane; i < out_words; i += 64)
+    dst[i] = (uint64_t)bits[2 * i] | ((uint64_t)bits[2 * i + 1] << 32);
+  if (__ballot(unsorted) && lane == 0) atomicOr(&ctr->error, kErrUnsorted);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_sorted(const uint64_t *__restrict__ offsets,
+                                                         const uint32_t *__restrict__ tokens,
+                                                         uint64_t n, JoinCounters *__restrict__ ctr) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t k = (uint64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (k >= n) return;
+  const uint64_t o0 = offsets[k], o1 = offsets[k + 1];
+  bool unsorted = false;
+  for (uint64_t t = o0 + lane; t + 1 < o1; t += 64) unsorted |= !(tokens[t] < tokens[t + 1]);
+  if (__ballot(unsorted) && lane == 0) atomicOr(&ctr->error, kErrUnsorted);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_bitmaps(const uint64_t *__restrict__ in,
+                                                           const uint32_t *__restrict__ perm,
+                                                           uint64_t n, uint32_t in_words,
+                                                           uint32_t out_words,
+                                                           uint64_t *__restrict__ out) {
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t x = e / out_words;
+  const uint32_t w = (uint32_t)(e - x * out_words);
+  if (x >= n) return;
+  const uint64_t k = perm[x];
+  out[e] = (w < in_words && k < n) ? in[k * in_words + w] : 0ull;
+}
+
+template <int METHOD>
+hipError_t launch_method(bool pow2, dim3 grid, hipStream_t st, const uint64_t *offsets,
+                         const uint32_t *tokens, const uint32_t *perm, uint64_t n,
+                         uint32_t b_bits, uint32_t out_words, uint64_t *out, JoinCounters *ctr) {
+  if (pow2)
+    hipLaunchKernelGGL((k_build_bitmaps<METHOD, true>), grid, dim3(kBlock), 0, st, offsets,
+                       tokens, perm, n, b_bits, out_words, out, ctr);
+  else
+    hipLaunchKernelGGL((k_build_bitmaps<METHOD, false>), grid, dim3(kBlock), 0, st, offsets,
+                       tokens, perm, n, b_bits, out_words, out, ctr);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
+                                const uint32_t *perm, uint64_t n, uint32_t b_bits, int method,
+                                uint32_t out_words, uint64_t *out, JoinCounters *ctr,
+                                hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (out_words > kMaxWords || out_words < b_bits / 64) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock));
+  bool pow2 = (b_bits & (b_bits - 1)) == 0;
+  switch (method) {
+    case SSJ_BM_XOR:
+      return launch_method<SSJ_BM_XOR>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+                                       out_words, out, ctr);
+    case SSJ_BM_SET:
+      return launch_method<SSJ_BM_SET>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+                                       out_words, out, ctr);
+    case SSJ_BM_NEXT:
+      return launch_method<SSJ_BM_NEXT>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+                                        out_words, out, ctr);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_check_sorted(const uint64_t *offsets, const uint32_t *tokens, uint64_t n,
+                               JoinCounters *ctr, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL(k_check_sorted, grid, dim3(kBlock), 0, st, offsets, tokens, n, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint64_t n,
+                                 uint32_t in_words, uint32_t out_words, uint64_t *out,
+                                 hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t total = n * out_words;
+  dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_gather_bitmaps, grid, dim3(kBlock), 0, st, in, perm, n, in_words,
+                     out_words, out);
+  return hipGetLastError();
+}
+
+}  // namespace ssj

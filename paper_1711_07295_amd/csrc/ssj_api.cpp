@@ -1,0 +1,556 @@
+// C-ABI host layer of the library: argument checks, the size-ordered
+// preparation of each collection, the tile plan of the length band, the
+// filter/verify rounds over a bounded survivor queue, and the emission of
+// the sorted result pairs.  Every step of the join runs in the library's
+// own kernels; the host only plans, launches and copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "ssj.h"
+#include "ssj_internal.h"
+
+namespace ssj {
+namespace {
+
+constexpr uint64_t kDefaultQueue = 1ull << 27;   // 1 GiB of (row, column) pairs
+constexpr uint32_t kDefaultTileCols = 4096;
+constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
+
+struct Fail {
+  int code;
+};
+
+inline void check(hipError_t e) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) throw Fail{SSJ_E_NOMEM};
+  throw Fail{SSJ_E_DEVICE};
+}
+
+// Stream-ordered device allocations of one call, released on every exit.
+class Arena {
+ public:
+  explicit Arena(hipStream_t st) : st_(st) {}
+  ~Arena() {
+    for (void *p : ptrs_) (void)hipFreeAsync(p, st_);
+  }
+  template <class T>
+  T *alloc(uint64_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, n * sizeof(T), st_);
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      throw Fail{SSJ_E_NOMEM};
+    }
+    ptrs_.push_back(p);
+    return static_cast<T *>(p);
+  }
+  void release(void *p) {
+    for (auto &q : ptrs_)
+      if (q == p) {
+        (void)hipFreeAsync(q, st_);
+        q = ptrs_.back();
+        ptrs_.pop_back();
+        return;
+      }
+  }
+
+ private:
+  hipStream_t st_;
+  std::vector<void *> ptrs_;
+};
+
+void keep_pool_memory() {
+  static std::once_flag once[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::call_once(once[dev], [dev] {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+}
+
+template <class T>
+void d2h(T *dst, const T *src, uint64_t n, hipStream_t st) {
+  if (n == 0) return;
+  check(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+template <class T>
+void h2d(T *dst, const T *src, uint64_t n, hipStream_t st) {
+  if (n == 0) return;
+  check(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
+}
+void sync(hipStream_t st) { check(hipStreamSynchronize(st)); }
+
+int bits_for(uint64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+// One collection, validated and in size order.
+struct Side {
+  const ssj_sets *in = nullptr;
+  uint64_t n = 0;
+  uint32_t max_size = 0;
+  uint32_t *sizes = nullptr;   // size order
+  uint32_t *perm = nullptr;    // size order -> caller index
+  uint32_t *sstart = nullptr;  // [max_size + 2]
+  std::vector<uint32_t> sstart_h;
+  uint64_t *bm = nullptr;      // size order, padded words
+  uint32_t first_nonempty() const { return sstart_h.size() > 1 ? sstart_h[1] : (uint32_t)n; }
+  uint64_t count_of(uint32_t s) const { return (uint64_t)sstart_h[s + 1] - sstart_h[s]; }
+};
+
+void validate_sets(const ssj_sets *s) {
+  if (!s) throw Fail{SSJ_E_INVALID};
+  if (s->n_sets >= 0xFFFFFFFFull) throw Fail{SSJ_E_INVALID};
+  if (s->n_sets > 0 && !s->offsets) throw Fail{SSJ_E_INVALID};
+  if (s->n_tokens > 0 && !s->tokens) throw Fail{SSJ_E_INVALID};
+}
+
+// Sizes, offsets check, stable size sort, group starts; bitmaps in size
+// order with `wpad` words (built with Bitmap-Xor, or gathered from the
+// caller's).  The token-order check is left in ctr->error.
+void prepare(Side &sd, const ssj_sets *s, const uint64_t *bm_caller, uint32_t b_bits,
+             uint32_t wpad, Arena &ar, JoinCounters *ctr, JoinCounters *ctr_h, hipStream_t st) {
+  sd.in = s;
+  sd.n = s->n_sets;
+  const uint64_t n = sd.n;
+  unsigned long long *keys = ar.alloc<unsigned long long>(n);
+  check(launch_set_sizes(s->offsets, n, s->n_tokens, keys, ctr, st));
+  d2h(ctr_h, ctr, 1, st);
+  sync(st);
+  if (ctr_h->error & (kErrOffsets | kErrTooBig)) throw Fail{SSJ_E_INVALID};
+  if (n == 0 && s->n_tokens != 0) throw Fail{SSJ_E_INVALID};
+  sd.max_size = ctr_h->max_size;
+  if ((uint64_t)sd.max_size * 2 + 2 > kMaxTable) throw Fail{SSJ_E_UNSUPPORTED};
+
+  // stable sort by size: keys (size << 32 | index), digits of the size only
+  unsigned long long *tmp = ar.alloc<unsigned long long>(n);
+  uint32_t *scr = ar.alloc<uint32_t>(radix_scratch_words(n));
+  int shifts[4], ns = 0;
+  for (int b = 0; b < bits_for(sd.max_size); b += 8) shifts[ns++] = 32 + b;
+  unsigned long long *sorted = keys;
+  check(radix_sort_u64(keys, tmp, n, shifts, ns, scr, st, &sorted));
+  sd.sizes = ar.alloc<uint32_t>(n);
+  sd.perm = ar.alloc<uint32_t>(n);
+  check(launch_unpack_keys(sorted, n, sd.sizes, sd.perm, st));
+  ar.release(keys);
+  ar.release(tmp);
+  ar.release(scr);
+  sd.sstart = ar.alloc<uint32_t>((uint64_t)sd.max_size + 2);
+  check(launch_group_starts(sd.sizes, n, sd.max_size, sd.sstart, st));
+  sd.sstart_h.assign((size_t)sd.max_size + 2, 0);
+  d2h(sd.sstart_h.data(), sd.sstart, sd.sstart_h.size(), st);
+
+  sd.bm = ar.alloc<uint64_t>(n * wpad);
+  if (bm_caller) {
+    check(launch_gather_bitmaps(bm_caller, sd.perm, n, b_bits / 64, wpad, sd.bm, st));
+    check(launch_check_sorted(s->offsets, s->tokens, n, ctr, st));
+  } else {
+    check(launch_build_bitmaps(s->offsets, s->tokens, sd.perm, n, b_bits, SSJ_BM_XOR, wpad,
+                               sd.bm, ctr, st));
+  }
+  d2h(ctr_h, ctr, 1, st);
+  sync(st);  // sstart_h is needed by the planner
+  if (ctr_h->error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+}
+
+struct Plan {
+  std::vector<int32_t> slack;   // [maxA + maxB + 1]
+  std::vector<uint32_t> omin;   // [maxA + maxB + 1]
+  std::vector<uint32_t> cmin, cmax;  // [maxA + 1]
+  std::vector<RowBlock> blocks;
+  uint32_t n_tiles = 0;
+  uint64_t band_pairs = 0;
+};
+
+// Least overlap o with sim >= p/q for sizes summing to L (Jaccard, Table 1):
+// o / (L - o) >= p / q  <=>  (p + q) o >= p L.
+inline uint32_t jaccard_omin(uint64_t L, uint64_t p, uint64_t q) {
+  return (uint32_t)((p * L + (p + q) - 1) / (p + q));
+}
+
+void make_plan(Plan &pl, const Side &A, const Side &B, bool self, uint64_t p, uint64_t q,
+               uint32_t rows_per_block, uint32_t tile_cols) {
+  const uint64_t maxA = A.max_size, maxB = B.max_size;
+  pl.slack.resize(maxA + maxB + 1);
+  pl.omin.resize(maxA + maxB + 1);
+  for (uint64_t L = 0; L <= maxA + maxB; ++L) {
+    uint32_t o = jaccard_omin(L, p, q);
+    pl.omin[L] = o;
+    pl.slack[L] = (int32_t)((int64_t)L - 2 * (int64_t)o);
+  }
+  // Length filter (Table 2, Jaccard): t |r| <= |s| <= |r| / t.  Empty sets
+  // never pair: an empty row gets an empty range, and cmin >= 1 otherwise.
+  pl.cmin.resize(maxA + 1);
+  pl.cmax.resize(maxA + 1);
+  for (uint64_t a = 0; a <= maxA; ++a) {
+    if (a == 0) {
+      pl.cmin[a] = 0xFFFFFFFFu;
+      pl.cmax[a] = 0;
+      continue;
+    }
+    uint64_t lo = (p * a + q - 1) / q;   // ceil(p a / q)
+    uint64_t hi = (q * a) / p;           // floor(q a / p)
+    if (lo < 1) lo = 1;
+    pl.cmin[a] = (uint32_t)std::min<uint64_t>(lo, 0xFFFFFFFFull);
+    pl.cmax[a] = (uint32_t)std::min<uint64_t>(hi, 0xFFFFFFFFull);
+  }
+  auto col_lo = [&](uint64_t a) -> uint32_t {  // first column with size >= cmin[a]
+    uint64_t c = pl.cmin[a];
+    return c > maxB ? (uint32_t)B.n : B.sstart_h[c];
+  };
+  auto col_hi = [&](uint64_t a) -> uint32_t {  // first column with size > cmax[a]
+    uint64_t c = pl.cmax[a];
+    return c >= maxB ? (uint32_t)B.n : B.sstart_h[c + 1];
+  };
+
+  // band pairs, exactly
+  pl.band_pairs = 0;
+  for (uint64_t a = 1; a <= maxA; ++a) {
+    uint64_t cnt = A.count_of((uint32_t)a);
+    if (!cnt) continue;
+    if (self) {
+      pl.band_pairs += cnt * ((uint64_t)A.sstart_h[a] - col_lo(a)) + cnt * (cnt - 1) / 2;
+    } else {
+      uint64_t lo = col_lo(a), hi = col_hi(a);
+      if (hi > lo) pl.band_pairs += cnt * (hi - lo);
+    }
+  }
+
+  // row blocks of rows_per_block rows from the first non-empty row
+  pl.blocks.clear();
+  uint64_t tiles = 0;
+  const uint32_t e0 = A.first_nonempty();
+  uint32_t s_of = 0;  // size of the current row, advanced monotonically
+  auto size_at = [&](uint32_t row) {
+    while (s_of + 1 <= maxA && A.sstart_h[s_of + 1] <= row) ++s_of;
+    return s_of;
+  };
+  for (uint64_t r0 = e0; r0 < A.n; r0 += rows_per_block) {
+    const uint32_t row0 = (uint32_t)r0;
+    const uint32_t row_end = (uint32_t)std::min<uint64_t>(r0 + rows_per_block, A.n);
+    const uint32_t a0 = size_at(row0);
+    RowBlock rb;
+    rb.row0 = row0;
+    rb.tile_begin = (uint32_t)tiles;
+    uint64_t nt;
+    if (self) {
+      rb.col_begin = std::min(col_lo(a0), row0);
+      rb.col_end = row_end;
+      nt = ((uint64_t)row0 - rb.col_begin + tile_cols - 1) / tile_cols + 1;
+    } else {
+      // the last row of the block has the largest size
+      uint32_t s_save = s_of;
+      const uint32_t a1 = size_at(row_end - 1);
+      s_of = s_save;
+      rb.col_begin = col_lo(a0);
+      rb.col_end = std::max(col_hi(a1), rb.col_begin);
+      nt = ((uint64_t)rb.col_end - rb.col_begin + tile_cols - 1) / tile_cols;
+    }
+    tiles += nt;
+    if (tiles >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
+    pl.blocks.push_back(rb);
+  }
+  pl.n_tiles = (uint32_t)tiles;
+}
+
+struct Timer {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  Timer(const Timer &) = delete;
+  Timer &operator=(const Timer &) = delete;
+  Timer() {
+    check(hipEventCreate(&ev[0]));
+    check(hipEventCreate(&ev[1]));
+  }
+  ~Timer() {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+  }
+};
+
+int join(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint64_t *s_bm,
+         bool self, uint32_t b_bits, int sim, uint32_t p, uint32_t q, const ssj_options *opts,
+         ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!out) return SSJ_E_INVALID;
+  out->pairs = nullptr;
+  out->count = 0;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  try {
+    validate_sets(R);
+    if (!self) validate_sets(S);
+    if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
+    if (sim < SSJ_SIM_JACCARD || sim > SSJ_SIM_OVERLAP) return SSJ_E_INVALID;
+    if (p == 0 || q == 0 || p > q) return SSJ_E_INVALID;
+    if (sim != SSJ_SIM_JACCARD) return SSJ_E_UNSUPPORTED;
+    const uint32_t g = std::gcd(p, q);
+    p /= g;
+    q /= g;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    keep_pool_memory();
+
+    const uint32_t words = b_bits / 64;
+    const uint32_t wpad = filter_padded_words(words);
+    if (!wpad) return SSJ_E_UNSUPPORTED;
+    const FilterShape shape = filter_shape(wpad);
+    const uint32_t tile_cols = opts && opts->tile_cols ? opts->tile_cols : kDefaultTileCols;
+    const uint64_t cap = opts && opts->queue_capacity ? opts->queue_capacity : kDefaultQueue;
+    const bool survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
+
+    Arena ar(st);
+    Timer t_prep, t_emit;
+    JoinCounters *ctr = ar.alloc<JoinCounters>(1);
+    JoinCounters ctr_h;
+    check(launch_reset_all(ctr, st));
+    check(hipEventRecord(t_prep.ev[0], st));
+
+    Side A, B;
+    prepare(A, R, r_bm, b_bits, wpad, ar, ctr, &ctr_h, st);
+    if (!self) prepare(B, S, s_bm, b_bits, wpad, ar, ctr, &ctr_h, st);
+    const Side &Bc = self ? A : B;
+
+    Plan pl;
+    make_plan(pl, A, Bc, self, p, q, shape.rows, tile_cols);
+
+    int32_t *d_slack = ar.alloc<int32_t>(pl.slack.size());
+    uint32_t *d_omin = ar.alloc<uint32_t>(pl.omin.size());
+    uint32_t *d_cmin = ar.alloc<uint32_t>(pl.cmin.size());
+    uint32_t *d_cmax = ar.alloc<uint32_t>(pl.cmax.size());
+    RowBlock *d_blocks = ar.alloc<RowBlock>(pl.blocks.size());
+    uint32_t *d_tile_block = ar.alloc<uint32_t>(pl.n_tiles);
+    h2d(d_slack, pl.slack.data(), pl.slack.size(), st);
+    h2d(d_omin, pl.omin.data(), pl.omin.size(), st);
+    h2d(d_cmin, pl.cmin.data(), pl.cmin.size(), st);
+    h2d(d_cmax, pl.cmax.data(), pl.cmax.size(), st);
+    h2d(d_blocks, pl.blocks.data(), pl.blocks.size(), st);
+    check(launch_expand_tiles(d_blocks, (uint32_t)pl.blocks.size(), pl.n_tiles, d_tile_block,
+                              st));
+    check(hipEventRecord(t_prep.ev[1], st));
+
+    // filter / verify rounds
+    // A queue reservation covers one step of U columns for all of a wave's
+    // rows; the queue must hold the largest such batch, or a full step could
+    // never be written and its tile could never be resumed.
+    const uint64_t qcap = std::max<uint64_t>(std::max<uint64_t>(shape.batch, 4096),
+                                             std::min<uint64_t>(cap, pl.band_pairs + 1));
+    uint2 *queue = ar.alloc<uint2>(qcap);
+    const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
+    Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
+    uint64_t res_cap = std::max<uint64_t>(qcap, 1024);
+    unsigned long long *results = ar.alloc<unsigned long long>(res_cap);
+
+    std::deque<Timer> t_filter, t_verify;  // events must not move
+    uint32_t n_resume_in = 0;
+    uint64_t results_n = 0;
+    check(launch_reset_all(ctr, st));
+    for (;;) {
+      if (pl.n_tiles == 0) break;
+      FilterConfig cfg;
+      cfg.n_rows = (uint32_t)A.n;
+      cfg.n_cols = (uint32_t)Bc.n;
+      cfg.n_tiles = pl.n_tiles;
+      cfg.tile_cols = tile_cols;
+      cfg.self = self ? 1u : 0u;
+      cfg.n_resume_in = n_resume_in;
+      cfg.n_blocks = (uint32_t)pl.blocks.size();
+      cfg.resume_cap = max_waves;
+      cfg.cap = qcap;
+      t_filter.emplace_back();
+      check(hipEventRecord(t_filter.back().ev[0], st));
+      check(launch_filter(wpad, A.bm, Bc.bm, A.sizes, Bc.sizes, Bc.sstart, d_slack, d_cmin,
+                          d_cmax, d_blocks, d_tile_block, queue, ctr, res_a, res_b, cfg, st));
+      check(hipEventRecord(t_filter.back().ev[1], st));
+      t_verify.emplace_back();
+      check(hipEventRecord(t_verify.back().ev[0], st));
+      check(launch_verify(queue, qcap, R->offsets, R->tokens, A.perm, self ? R->offsets : S->offsets,
+                          self ? R->tokens : S->tokens, Bc.perm, d_omin, (uint32_t)A.n,
+                          (uint32_t)Bc.n, self ? 1u : 0u,
+                          survivors_only ? 1u : 0u, results, res_cap, ctr, st));
+      check(hipEventRecord(t_verify.back().ev[1], st));
+      d2h(&ctr_h, ctr, 1, st);
+      sync(st);
+      if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+      results_n = ctr_h.results;
+      if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
+      if (!ctr_h.overflow) break;
+      // drain done; make room for another full queue of results, then resume
+      if (results_n + qcap > res_cap) {
+        uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
+        unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
+        check(launch_copy_u64(results, results_n, nr, st));
+        ar.release(results);
+        results = nr;
+        res_cap = ncap;
+      }
+      n_resume_in = ctr_h.n_resume;
+      std::swap(res_a, res_b);
+      check(launch_reset_round(ctr, st));
+    }
+    if (pl.n_tiles == 0) {
+      // nothing to filter; still report unsorted input
+      d2h(&ctr_h, ctr, 1, st);
+      sync(st);
+      if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+    }
+
+    // emit: sort keys (i << 32 | j) by j's digits then i's, copy out
+    check(hipEventRecord(t_emit.ev[0], st));
+    ssj_pair *host = nullptr;
+    if (results_n) {
+      unsigned long long *tmp = ar.alloc<unsigned long long>(results_n);
+      uint32_t *scr = ar.alloc<uint32_t>(radix_scratch_words(results_n));
+      int shifts[8], ns = 0;
+      const int bi = bits_for(A.n ? A.n - 1 : 0), bj = bits_for(Bc.n ? Bc.n - 1 : 0);
+      for (int b = 0; b < bj; b += 8) shifts[ns++] = b;
+      for (int b = 0; b < bi; b += 8) shifts[ns++] = 32 + b;
+      unsigned long long *sorted = results;
+      check(radix_sort_u64(results, tmp, results_n, shifts, ns, scr, st, &sorted));
+      ssj_pair *dpairs = ar.alloc<ssj_pair>(results_n);
+      check(launch_keys_to_pairs(sorted, results_n, dpairs, st));
+      host = static_cast<ssj_pair *>(std::malloc(results_n * sizeof(ssj_pair)));
+      if (!host) throw Fail{SSJ_E_NOMEM};
+      hipError_t e = hipMemcpyAsync(host, dpairs, results_n * sizeof(ssj_pair),
+                                    hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        std::free(host);
+        check(e);
+      }
+    }
+    check(hipEventRecord(t_emit.ev[1], st));
+    sync(st);
+    out->pairs = host;
+    out->count = results_n;
+    if (stats) {
+      stats->band_pairs = pl.band_pairs;
+      stats->survivors = ctr_h.survivors;
+      stats->results = results_n;
+      stats->filter_launches = (uint32_t)t_filter.size();
+      stats->b_bits = b_bits;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, t_prep.ev[0], t_prep.ev[1]);
+      stats->ms_prepare = ms;
+      for (auto &t : t_filter) {
+        ms = 0;
+        (void)hipEventElapsedTime(&ms, t.ev[0], t.ev[1]);
+        stats->ms_filter += ms;
+      }
+      for (auto &t : t_verify) {
+        ms = 0;
+        (void)hipEventElapsedTime(&ms, t.ev[0], t.ev[1]);
+        stats->ms_verify += ms;
+      }
+      ms = 0;
+      (void)hipEventElapsedTime(&ms, t_emit.ev[0], t_emit.ev[1]);
+      stats->ms_emit = ms;
+    }
+  } catch (const Fail &f) {
+    std::free(out->pairs);
+    out->pairs = nullptr;
+    out->count = 0;
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    return SSJ_E_NOMEM;
+  }
+  if (stats) {
+    stats->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                               t_start)
+                          .count();
+  }
+  return SSJ_OK;
+}
+
+}  // namespace
+}  // namespace ssj
+
+extern "C" {
+
+int ssj_abi_version(void) { return SSJ_ABI_VERSION; }
+
+const char *ssj_status_string(int status) {
+  switch (status) {
+    case SSJ_OK: return "ok";
+    case SSJ_E_INVALID: return "invalid argument";
+    case SSJ_E_UNSORTED: return "a set is not strictly increasing";
+    case SSJ_E_NOMEM: return "out of memory";
+    case SSJ_E_DEVICE: return "device error";
+    case SSJ_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *bitmaps_dev,
+                      void *hip_stream) {
+  using namespace ssj;
+  try {
+    validate_sets(s);
+    if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
+    if (method < SSJ_BM_XOR || method > SSJ_BM_NEXT) return SSJ_E_UNSUPPORTED;
+    if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    keep_pool_memory();
+    Arena ar(st);
+    JoinCounters *ctr = ar.alloc<JoinCounters>(1);
+    JoinCounters ctr_h;
+    check(launch_reset_all(ctr, st));
+    unsigned long long *keys = ar.alloc<unsigned long long>(s->n_sets);
+    check(launch_set_sizes(s->offsets, s->n_sets, s->n_tokens, keys, ctr, st));
+    d2h(&ctr_h, ctr, 1, st);
+    sync(st);
+    if (ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
+    if (s->n_sets == 0) return s->n_tokens ? SSJ_E_INVALID : SSJ_OK;
+    check(launch_build_bitmaps(s->offsets, s->tokens, nullptr, s->n_sets, b_bits, method,
+                               b_bits / 64, bitmaps_dev, ctr, st));
+    d2h(&ctr_h, ctr, 1, st);
+    sync(st);
+    if (ctr_h.error & kErrUnsorted) return SSJ_E_UNSORTED;
+  } catch (const Fail &f) {
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    return SSJ_E_NOMEM;
+  }
+  return SSJ_OK;
+}
+
+int ssj_self_join(const ssj_sets *s, const uint64_t *bitmaps_dev, uint32_t b_bits, int sim,
+                  uint32_t p, uint32_t q, const ssj_options *opts, ssj_pairs *out,
+                  ssj_stats *stats, void *hip_stream) {
+  return ssj::join(s, bitmaps_dev, s, bitmaps_dev, true, b_bits, sim, p, q, opts, out, stats,
+                   hip_stream);
+}
+
+int ssj_rs_join(const ssj_sets *r, const uint64_t *r_bitmaps_dev, const ssj_sets *s,
+                const uint64_t *s_bitmaps_dev, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
+                const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
+  if ((r_bitmaps_dev == nullptr) != (s_bitmaps_dev == nullptr)) return SSJ_E_INVALID;
+  return ssj::join(r, r_bitmaps_dev, s, s_bitmaps_dev, false, b_bits, sim, p, q, opts, out, stats,
+                   hip_stream);
+}
+
+void ssj_free_pairs(ssj_pairs *out) {
+  if (!out) return;
+  std::free(out->pairs);
+  out->pairs = nullptr;
+  out->count = 0;
+}
+
+}  // extern "C"

@@ -155,3 +155,16 @@ def test_banded_rows_subset():
 def test_size_order():
     c = gen.from_lists([[1, 2, 3], [4], [5, 6], [7], []])
     assert oracle.size_order(c.offsets).tolist() == [4, 1, 3, 2, 0]
+
+
+def test_check_pairs_agrees_with_join():
+    c = gen.generate(n_sets=800, universe=90, zipf_s=1.0, size_lo=1, size_hi=12,
+                     planted_frac=0.2, seed=41)
+    res = oracle.self_join(c.offsets, c.tokens, 3, 5)
+    assert oracle.check_pairs(c.offsets, c.tokens, c.offsets, c.tokens, res, 3, 5).all()
+    found = set(map(tuple, res.tolist()))
+    rng = np.random.default_rng(1)
+    cand = rng.integers(0, 800, size=(3000, 2)).astype(np.uint32)
+    cand = cand[cand[:, 0] < cand[:, 1]]
+    ok = oracle.check_pairs(c.offsets, c.tokens, c.offsets, c.tokens, cand, 3, 5)
+    assert ok.tolist() == [tuple(x) in found for x in cand.tolist()]
