@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--q", type=int, default=5)
     ap.add_argument("--bits", type=int, default=128)
+    ap.add_argument("--tile-cols", type=int, default=0, help="0 = the library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -78,7 +79,7 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        return ssj.ssj_self_join(dev, args.p, args.q, b_bits=args.bits)
+        return ssj.ssj_self_join(dev, args.p, args.q, b_bits=args.bits, tile_cols=args.tile_cols)
 
     for w in range(args.warmup):
         pairs, st = step()

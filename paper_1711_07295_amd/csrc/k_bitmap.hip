@@ -70,6 +70,62 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps(
   if (__ballot(unsorted) && lane == 0) atomicOr(&ctr->error, kErrUnsorted);
 }
 
+// Narrow bitmaps (up to 8 words), XOR or SET: a workgroup takes kSegSets
+// consecutive sets in caller order, whose tokens are one contiguous run of
+// the CSR array, and reads that run fully coalesced.  Each token finds its
+// set by binary search over the segment's offsets in LDS and flips (or sets)
+// its bit in the set's LDS bitmap; the bitmaps are then written to their
+// output rows (rank[k] when the output is in size order).
+constexpr uint32_t kSegSets = 256;
+
+template <int WO, int METHOD, bool POW2>
+__global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
+    const uint64_t *__restrict__ offsets, const uint32_t *__restrict__ tokens,
+    const uint32_t *__restrict__ rank, uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out,
+    JoinCounters *__restrict__ ctr) {
+  __shared__ uint64_t soff[kSegSets + 1];
+  __shared__ uint32_t sbits[kSegSets * 2 * WO];
+  const uint64_t s0 = (uint64_t)blockIdx.x * kSegSets;
+  const uint32_t ns = (uint32_t)min((uint64_t)kSegSets, n - s0);
+  const uint64_t t0 = offsets[s0];
+  for (uint32_t i = threadIdx.x; i <= ns; i += kBlock) soff[i] = offsets[s0 + i] - t0;
+  for (uint32_t i = threadIdx.x; i < ns * 2 * WO; i += kBlock) sbits[i] = 0;
+  __syncthreads();
+  const uint64_t nt = soff[ns];
+  const uint32_t mask = b_bits - 1;
+  bool unsorted = false;
+  for (uint64_t g = threadIdx.x; g < nt; g += kBlock) {
+    uint32_t lo = 0, hi = ns;  // soff[lo] <= g < soff[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (soff[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint32_t v = tokens[t0 + g];
+    if (g + 1 < soff[lo + 1]) unsorted |= !(v < tokens[t0 + g + 1]);
+    const uint32_t s = POW2 ? (v & mask) : (v % b_bits);
+    if (METHOD == SSJ_BM_XOR) atomicXor(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+    else atomicOr(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < ns * WO; i += kBlock) {
+    const uint32_t x = i / WO, w = i - x * WO;
+    const uint64_t row = rank ? rank[s0 + x] : s0 + x;
+    if (row < n)
+      out[row * WO + w] = (uint64_t)sbits[x * 2 * WO + 2 * w] |
+                          ((uint64_t)sbits[x * 2 * WO + 2 * w + 1] << 32);
+  }
+  if (__ballot(unsorted) && (threadIdx.x & 63) == 0) atomicOr(&ctr->error, kErrUnsorted);
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert_perm(const uint32_t *__restrict__ perm,
+                                                        uint64_t n, uint32_t *__restrict__ rank) {
+  const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (x < n) {
+    const uint32_t k = perm[x];
+    if (k < n) rank[k] = (uint32_t)x;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_sorted(const uint64_t *__restrict__ offsets,
                                                          const uint32_t *__restrict__ tokens,
                                                          uint64_t n, JoinCounters *__restrict__ ctr) {
@@ -95,10 +151,38 @@ __global__ __launch_bounds__(kBlock) void k_gather_bitmaps(const uint64_t *__res
   out[e] = (w < in_words && k < n) ? in[k * in_words + w] : 0ull;
 }
 
+template <int WO, int METHOD>
+hipError_t launch_seg(bool pow2, hipStream_t st, const uint64_t *offsets,
+                      const uint32_t *tokens, const uint32_t *rank, uint64_t n, uint32_t b_bits,
+                      uint64_t *out, JoinCounters *ctr) {
+  dim3 grid((unsigned)((n + kSegSets - 1) / kSegSets));
+  if (pow2)
+    hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, true>), grid, dim3(kBlock), 0, st,
+                       offsets, tokens, rank, n, b_bits, out, ctr);
+  else
+    hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, false>), grid, dim3(kBlock), 0, st,
+                       offsets, tokens, rank, n, b_bits, out, ctr);
+  return hipGetLastError();
+}
+
 template <int METHOD>
 hipError_t launch_method(bool pow2, dim3 grid, hipStream_t st, const uint64_t *offsets,
-                         const uint32_t *tokens, const uint32_t *perm, uint64_t n,
-                         uint32_t b_bits, uint32_t out_words, uint64_t *out, JoinCounters *ctr) {
+                         const uint32_t *tokens, const uint32_t *perm, const uint32_t *rank,
+                         uint64_t n, uint32_t b_bits, uint32_t out_words, uint64_t *out,
+                         JoinCounters *ctr) {
+  if (METHOD != SSJ_BM_NEXT && (rank || !perm)) {
+    switch (out_words) {
+      case 1: return launch_seg<1, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 2: return launch_seg<2, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 3: return launch_seg<3, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 4: return launch_seg<4, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 5: return launch_seg<5, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 6: return launch_seg<6, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 7: return launch_seg<7, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      case 8: return launch_seg<8, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      default: break;
+    }
+  }
   if (pow2)
     hipLaunchKernelGGL((k_build_bitmaps<METHOD, true>), grid, dim3(kBlock), 0, st, offsets,
                        tokens, perm, n, b_bits, out_words, out, ctr);
@@ -111,7 +195,8 @@ hipError_t launch_method(bool pow2, dim3 grid, hipStream_t st, const uint64_t *o
 }  // namespace
 
 hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
-                                const uint32_t *perm, uint64_t n, uint32_t b_bits, int method,
+                                const uint32_t *perm, const uint32_t *rank, uint64_t n,
+                                uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
                                 hipStream_t st) {
   if (n == 0) return hipSuccess;
@@ -120,13 +205,13 @@ hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
   bool pow2 = (b_bits & (b_bits - 1)) == 0;
   switch (method) {
     case SSJ_BM_XOR:
-      return launch_method<SSJ_BM_XOR>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+      return launch_method<SSJ_BM_XOR>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
                                        out_words, out, ctr);
     case SSJ_BM_SET:
-      return launch_method<SSJ_BM_SET>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+      return launch_method<SSJ_BM_SET>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
                                        out_words, out, ctr);
     case SSJ_BM_NEXT:
-      return launch_method<SSJ_BM_NEXT>(pow2, grid, st, offsets, tokens, perm, n, b_bits,
+      return launch_method<SSJ_BM_NEXT>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
                                         out_words, out, ctr);
     default:
       return hipErrorInvalidValue;
@@ -152,4 +237,13 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
   return hipGetLastError();
 }
 
+}  // namespace ssj
+
+namespace ssj {
+hipError_t launch_invert_perm(const uint32_t *perm, uint64_t n, uint32_t *rank, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_invert_perm, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     st, perm, n, rank);
+  return hipGetLastError();
+}
 }  // namespace ssj

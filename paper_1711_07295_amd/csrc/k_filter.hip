@@ -55,12 +55,26 @@ struct Sink {
   uint32_t resume_cap;
 };
 
+// popcount(x) + acc as one v_bcnt_u32_b32.  Written out so that the sum over
+// a bitmap's words stays one accumulating chain (the compiler would otherwise
+// split it into parallel chains joined by an extra add).
+__device__ __forceinline__ uint32_t bcnt_first(uint32_t x) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, 0" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
 template <int W, int R, bool DIAG>
 __device__ __forceinline__ bool keep(const Rows<W, R> &rw, const uint32_t *cb, int r,
                                      int32_t thr, uint32_t j) {
-  uint32_t h = 0;
+  uint32_t h = bcnt_first(rw.bits[r][0] ^ cb[0]);
 #pragma unroll
-  for (int e = 0; e < 2 * W; ++e) h = __builtin_popcount(rw.bits[r][e] ^ cb[e]) + h;
+  for (int e = 1; e < 2 * W; ++e) h = bcnt_acc(rw.bits[r][e] ^ cb[e], h);
   bool k = (int32_t)h <= thr;
   if (DIAG) k = k && (j < rw.idx[r]);
   return k;
@@ -118,13 +132,30 @@ template <int W, int R, int U, bool DIAG>
 __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
                                       const int32_t (&thr)[R], uint32_t j, uint32_t g1,
                                       const Sink &sink) {
-  for (; j + U <= g1; j += U) {
-    uint32_t cb[U][2 * W];
+  // Scalar loads may return out of order, so a wave can only wait for all
+  // of them; the next step's columns are therefore requested right after the
+  // wait for the current step and arrive while the current step computes.
+  uint32_t nb[U][2 * W];
+  if (j + U <= g1) {
     const uint32_t *p = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)j * W);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int e = 0; e < 2 * W; ++e) cb[u][e] = p[u * 2 * W + e];
+      for (int e = 0; e < 2 * W; ++e) nb[u][e] = p[u * 2 * W + e];
+  }
+  for (; j + U <= g1; j += U) {
+    uint32_t cb[U][2 * W];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < 2 * W; ++e) cb[u][e] = nb[u][e];
+    if (j + 2 * U <= g1) {
+      const uint32_t *p = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)(j + U) * W);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 2 * W; ++e) nb[u][e] = p[u * 2 * W + e];
+    }
     unsigned long long any = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -173,13 +204,28 @@ __global__ __launch_bounds__(kBlock) void k_filter(
     t = rfl(resume_in[wave].tile);
     col = rfl(resume_in[wave].col);
   }
+  // Workgroups are dispatched to the XCDs round-robin: start in this XCD's
+  // partition of the tile list, move on to the others when it runs dry.
+  uint32_t part = blockIdx.x % kParts, parts_left = kParts;
   for (;;) {
     if (!resumed) {
       if (__hip_atomic_load(&ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-      uint32_t tt = 0;
-      if (lane == 0) tt = atomicAdd(&ctr->tile_next, 1u);
-      t = rfl(tt);
-      if (t >= cfg.n_tiles) return;
+      bool got = false;
+      while (parts_left) {
+        const uint32_t p0 = (uint32_t)(((uint64_t)cfg.n_tiles * part) / kParts);
+        const uint32_t p1 = (uint32_t)(((uint64_t)cfg.n_tiles * (part + 1)) / kParts);
+        uint32_t tt = 0;
+        if (lane == 0) tt = atomicAdd(&ctr->tile_next[part][0], 1u);
+        tt = rfl(tt);
+        if (tt < p1 - p0) {
+          t = p0 + tt;
+          got = true;
+          break;
+        }
+        part = part + 1 == kParts ? 0 : part + 1;
+        --parts_left;
+      }
+      if (!got) return;
     }
     // decode the tile
     const uint32_t b = rfl(tile_block[t]);

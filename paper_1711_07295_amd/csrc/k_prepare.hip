@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kBlock) void k_set_sizes(const uint64_t *__restrict
     }
     keys[k] = ((unsigned long long)sz32 << 32) | k;
   }
-  // wave-level reduction before the global atomics
+  // workgroup reduction, then at most one atomic per workgroup, skipped when
+  // the running maximum is already as large
+  __shared__ uint32_t wmax[kBlock / 64], werr[kBlock / 64];
   uint32_t m = sz32;
   for (int d = 32; d >= 1; d >>= 1) {
     uint32_t o = __shfl_xor(m, d, 64);
@@ -38,7 +40,17 @@ __global__ __launch_bounds__(kBlock) void k_set_sizes(const uint64_t *__restrict
   uint32_t e = err;
   for (int d = 32; d >= 1; d >>= 1) e |= __shfl_xor(e, d, 64);
   if ((threadIdx.x & 63) == 0) {
-    if (m) atomicMax(&ctr->max_size, m);
+    wmax[threadIdx.x >> 6] = m;
+    werr[threadIdx.x >> 6] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      m = wmax[w] > m ? wmax[w] : m;
+      e |= werr[w];
+    }
+    if (m > __hip_atomic_load(&ctr->max_size, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&ctr->max_size, m);
     if (e) atomicOr(&ctr->error, e);
   }
 }
@@ -76,7 +88,7 @@ __global__ void k_reset_round(JoinCounters *ctr) {
 
 __global__ void k_reset_all(JoinCounters *ctr) {
   uint32_t *w = reinterpret_cast<uint32_t *>(ctr);
-  if (threadIdx.x < sizeof(JoinCounters) / 4) w[threadIdx.x] = 0;
+  for (uint32_t i = threadIdx.x; i < sizeof(JoinCounters) / 4; i += blockDim.x) w[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_keys_to_pairs(const unsigned long long *__restrict__ keys,

@@ -15,7 +15,7 @@ constexpr int kItems = 8;                 // keys per thread
 constexpr int kTile = kBlock * kItems;    // keys per workgroup
 constexpr int kWaves = kBlock / 64;
 constexpr int kWaveKeys = kTile / kWaves; // contiguous keys per wave
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ __forceinline__ uint32_t digit_of(unsigned long long k, int shift) {
@@ -46,14 +46,32 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const unsigned long long 
 
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const unsigned long long *__restrict__ keys, unsigned long long *__restrict__ out, uint64_t n,
-    int shift, uint32_t nblocks, const uint32_t *__restrict__ hist_scanned) {
+    int shift, uint32_t nblocks, const uint32_t *__restrict__ hist_scanned,
+    const uint32_t *__restrict__ totals) {
+  static_assert(kBlock == 256, "one thread per digit");
   __shared__ uint32_t wcnt[kWaves][256];
   __shared__ uint32_t gbase[256];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < kWaves * 256; d += kBlock) (&wcnt[0][0])[d] = 0;
-  for (int d = threadIdx.x; d < 256; d += kBlock)
-    gbase[d] = hist_scanned[(uint64_t)d * nblocks + blockIdx.x];
+  // digit bases: exclusive scan of the 256 digit totals, plus this block's
+  // offset inside its digit
+  {
+    __shared__ uint32_t wtot[kWaves];
+    const int d = threadIdx.x;  // kBlock == 256 digits
+    const uint32_t tot = totals[d];
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) wtot[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int v = 0; v < w; ++v) pre += wtot[v];
+    gbase[d] = pre + inc - tot + hist_scanned[(uint64_t)d * nblocks + blockIdx.x];
+  }
   __syncthreads();
 
   const uint64_t wbase = (uint64_t)blockIdx.x * kTile + (uint64_t)w * kWaveKeys;
@@ -100,88 +118,59 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
   }
 }
 
-// exclusive scan of kScanTile entries per workgroup; block totals to `sums`
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *__restrict__ data, uint64_t m,
-                                                       uint32_t *__restrict__ sums) {
+// One workgroup per digit: exclusive scan, in place, of that digit's counts
+// over all sort blocks (hist[d * nblocks + b]), and the digit's total.
+__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *__restrict__ hist,
+                                                             uint32_t nblocks,
+                                                             uint32_t *__restrict__ totals) {
   __shared__ uint32_t wsum[kWaves];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t tsum = 0;
+  uint32_t *row = hist + (uint64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nblocks; base += kScanTile) {
+    const uint32_t first = base + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t tsum = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < m ? data[base + i] : 0u;
-    tsum += v[i];
-  }
-  // inclusive wave scan of the thread totals
-  uint32_t inc = tsum;
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = first + i < nblocks ? row[first + i] : 0u;
+      tsum += v[i];
+    }
+    uint32_t inc = tsum;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
-  }
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  uint32_t wpre = 0, total = 0;
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t wpre = 0, total = 0;
 #pragma unroll
-  for (int v2 = 0; v2 < kWaves; ++v2) {
-    uint32_t s = wsum[v2];
-    if (v2 < w) wpre += s;
-    total += s;
-  }
-  uint32_t run = wpre + inc - tsum;
+    for (int v2 = 0; v2 < kWaves; ++v2) {
+      uint32_t s2 = wsum[v2];
+      if (v2 < w) wpre += s2;
+      total += s2;
+    }
+    uint32_t run = carry + wpre + inc - tsum;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < m) data[base + i] = run;
-    run += v[i];
+    for (int i = 0; i < kScanItems; ++i) {
+      if (first + i < nblocks) row[first + i] = run;
+      run += v[i];
+    }
+    carry += total;
+    __syncthreads();  // wsum is rewritten by the next chunk
   }
-  if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *__restrict__ data, uint64_t m,
-                                                     const uint32_t *__restrict__ sums) {
-  uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  uint32_t add = sums[blockIdx.x];
-  for (int i = threadIdx.x; i < kScanTile; i += kBlock)
-    if (base + i < m) data[base + i] += add;
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
-
-uint64_t scan_scratch_words(uint64_t m) {
-  uint64_t total = 0;
-  while (m > (uint64_t)kScanTile) {
-    m = cdiv(m, kScanTile);
-    total += m;
-  }
-  return total + 1;
-}
-
-// in-place exclusive scan of data[0..m); scratch holds scan_scratch_words(m)
-hipError_t scan_exclusive(uint32_t *data, uint64_t m, uint32_t *scratch, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  uint64_t nb = cdiv(m, kScanTile);
-  if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, st, data, m, (uint32_t *)nullptr);
-    return hipGetLastError();
-  }
-  uint32_t *sums = scratch;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kBlock), 0, st, data, m, sums);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = scan_exclusive(sums, nb, scratch + nb, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, st, data, m, sums);
-  return hipGetLastError();
-}
 
 }  // namespace
 
 uint64_t radix_scratch_words(uint64_t n) {
   uint64_t nb = cdiv(n ? n : 1, kTile);
-  uint64_t m = 256 * nb;
-  return m + scan_scratch_words(m);
+  return 256 * nb + 256;
 }
 
 hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n,
@@ -192,18 +181,16 @@ hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uin
   uint64_t nb = cdiv(n, kTile);
   if (nb > 0xFFFFFFFFull / 256) return hipErrorInvalidValue;
   uint32_t *hist = scratch;
-  uint32_t *sscr = scratch + 256 * nb;
+  uint32_t *totals = scratch + 256 * nb;
   unsigned long long *src = keys, *dst = tmp;
   for (int p = 0; p < n_shifts; ++p) {
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, st, src, n, shifts[p],
                        (uint32_t)nb, hist);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = scan_exclusive(hist, 256 * nb, sscr, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kBlock), 0, st, hist, (uint32_t)nb,
+                       totals);
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, st, src, dst, n,
-                       shifts[p], (uint32_t)nb, hist);
-    e = hipGetLastError();
+                       shifts[p], (uint32_t)nb, hist, totals);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned long long *t = src;
     src = dst;

@@ -34,52 +34,88 @@ inline void check(hipError_t e) {
   throw Fail{SSJ_E_DEVICE};
 }
 
-// Stream-ordered device allocations of one call, released on every exit.
-class Arena {
+// Device memory chunks kept between calls, per device.  A call takes chunks
+// at its start and gives them back only after its final stream
+// synchronisation, so a chunk is never in use by two calls.  Chunk sizes are
+// powers of two (at least 64 MiB), so a chunk fits any later request of up to
+// its size.  The cache lives until the process ends.
+class ChunkCache {
  public:
-  explicit Arena(hipStream_t st) : st_(st) {}
-  ~Arena() {
-    for (void *p : ptrs_) (void)hipFreeAsync(p, st_);
+  static ChunkCache &get() {
+    static ChunkCache c;
+    return c;
   }
-  template <class T>
-  T *alloc(uint64_t n) {
-    if (n == 0) n = 1;
-    void *p = nullptr;
-    hipError_t e = hipMallocAsync(&p, n * sizeof(T), st_);
-    if (e != hipSuccess || p == nullptr) {
-      (void)hipGetLastError();
-      throw Fail{SSJ_E_NOMEM};
+  void *take(int dev, uint64_t size) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto &v = free_[dev & 63];
+      for (size_t k = 0; k < v.size(); ++k)
+        if (v[k].size == size) {
+          void *p = v[k].ptr;
+          v[k] = v.back();
+          v.pop_back();
+          return p;
+        }
     }
-    ptrs_.push_back(p);
-    return static_cast<T *>(p);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, size);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
   }
-  void release(void *p) {
-    for (auto &q : ptrs_)
-      if (q == p) {
-        (void)hipFreeAsync(q, st_);
-        q = ptrs_.back();
-        ptrs_.pop_back();
-        return;
-      }
+  void give(int dev, void *p, uint64_t size) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_[dev & 63].push_back({p, size});
   }
 
  private:
-  hipStream_t st_;
-  std::vector<void *> ptrs_;
+  struct Chunk {
+    void *ptr;
+    uint64_t size;
+  };
+  std::mutex mu_;
+  std::vector<Chunk> free_[64];
 };
 
-void keep_pool_memory() {
-  static std::once_flag once[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  std::call_once(once[dev], [dev] {
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+// Device memory of one call, carved from cached chunks.  The destructor
+// returns the chunks; every exit path synchronises the stream first.
+class Arena {
+ public:
+  explicit Arena(hipStream_t st) : st_(st) {
+    if (hipGetDevice(&dev_) != hipSuccess) dev_ = 0;
+  }
+  ~Arena() {
+    (void)hipStreamSynchronize(st_);
+    for (auto &c : chunks_) ChunkCache::get().give(dev_, c.first, c.second);
+  }
+  template <class T>
+  T *alloc(uint64_t n) {
+    uint64_t bytes = (std::max<uint64_t>(n, 1) * sizeof(T) + 255) & ~255ull;
+    if (bytes > left_) {
+      uint64_t size = kChunk;
+      while (size < bytes) size <<= 1;
+      void *p = ChunkCache::get().take(dev_, size);
+      if (!p) throw Fail{SSJ_E_NOMEM};
+      chunks_.push_back({p, size});
+      next_ = static_cast<char *>(p);
+      left_ = size;
     }
-  });
-}
+    T *out = reinterpret_cast<T *>(next_);
+    next_ += bytes;
+    left_ -= bytes;
+    return out;
+  }
+
+ private:
+  static constexpr uint64_t kChunk = 64ull << 20;
+  hipStream_t st_;
+  int dev_ = 0;
+  std::vector<std::pair<void *, uint64_t>> chunks_;
+  char *next_ = nullptr;
+  uint64_t left_ = 0;
+};
 
 template <class T>
 void d2h(T *dst, const T *src, uint64_t n, hipStream_t st) {
@@ -150,9 +186,6 @@ void prepare(Side &sd, const ssj_sets *s, const uint64_t *bm_caller, uint32_t b_
   sd.sizes = ar.alloc<uint32_t>(n);
   sd.perm = ar.alloc<uint32_t>(n);
   check(launch_unpack_keys(sorted, n, sd.sizes, sd.perm, st));
-  ar.release(keys);
-  ar.release(tmp);
-  ar.release(scr);
   sd.sstart = ar.alloc<uint32_t>((uint64_t)sd.max_size + 2);
   check(launch_group_starts(sd.sizes, n, sd.max_size, sd.sstart, st));
   sd.sstart_h.assign((size_t)sd.max_size + 2, 0);
@@ -163,7 +196,9 @@ void prepare(Side &sd, const ssj_sets *s, const uint64_t *bm_caller, uint32_t b_
     check(launch_gather_bitmaps(bm_caller, sd.perm, n, b_bits / 64, wpad, sd.bm, st));
     check(launch_check_sorted(s->offsets, s->tokens, n, ctr, st));
   } else {
-    check(launch_build_bitmaps(s->offsets, s->tokens, sd.perm, n, b_bits, SSJ_BM_XOR, wpad,
+    uint32_t *rank = ar.alloc<uint32_t>(n);
+    check(launch_invert_perm(sd.perm, n, rank, st));
+    check(launch_build_bitmaps(s->offsets, s->tokens, sd.perm, rank, n, b_bits, SSJ_BM_XOR, wpad,
                                sd.bm, ctr, st));
   }
   d2h(ctr_h, ctr, 1, st);
@@ -304,7 +339,6 @@ int join(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint6
     p /= g;
     q /= g;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    keep_pool_memory();
 
     const uint32_t words = b_bits / 64;
     const uint32_t wpad = filter_padded_words(words);
@@ -329,17 +363,22 @@ int join(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint6
     Plan pl;
     make_plan(pl, A, Bc, self, p, q, shape.rows, tile_cols);
 
-    int32_t *d_slack = ar.alloc<int32_t>(pl.slack.size());
-    uint32_t *d_omin = ar.alloc<uint32_t>(pl.omin.size());
-    uint32_t *d_cmin = ar.alloc<uint32_t>(pl.cmin.size());
-    uint32_t *d_cmax = ar.alloc<uint32_t>(pl.cmax.size());
-    RowBlock *d_blocks = ar.alloc<RowBlock>(pl.blocks.size());
+    // the plan's tables go up in one copy: blocks, slack, omin, cmin, cmax
+    const uint64_t nL = pl.slack.size(), nA = pl.cmin.size(), nB = pl.blocks.size();
+    std::vector<uint32_t> packed(4 * nB + 2 * nL + 2 * nA);
+    std::memcpy(packed.data(), pl.blocks.data(), nB * sizeof(RowBlock));
+    std::memcpy(packed.data() + 4 * nB, pl.slack.data(), nL * 4);
+    std::memcpy(packed.data() + 4 * nB + nL, pl.omin.data(), nL * 4);
+    std::memcpy(packed.data() + 4 * nB + 2 * nL, pl.cmin.data(), nA * 4);
+    std::memcpy(packed.data() + 4 * nB + 2 * nL + nA, pl.cmax.data(), nA * 4);
+    uint32_t *d_packed = ar.alloc<uint32_t>(packed.size());
+    h2d(d_packed, packed.data(), packed.size(), st);
+    RowBlock *d_blocks = reinterpret_cast<RowBlock *>(d_packed);
+    int32_t *d_slack = reinterpret_cast<int32_t *>(d_packed + 4 * nB);
+    uint32_t *d_omin = d_packed + 4 * nB + nL;
+    uint32_t *d_cmin = d_packed + 4 * nB + 2 * nL;
+    uint32_t *d_cmax = d_packed + 4 * nB + 2 * nL + nA;
     uint32_t *d_tile_block = ar.alloc<uint32_t>(pl.n_tiles);
-    h2d(d_slack, pl.slack.data(), pl.slack.size(), st);
-    h2d(d_omin, pl.omin.data(), pl.omin.size(), st);
-    h2d(d_cmin, pl.cmin.data(), pl.cmin.size(), st);
-    h2d(d_cmax, pl.cmax.data(), pl.cmax.size(), st);
-    h2d(d_blocks, pl.blocks.data(), pl.blocks.size(), st);
     check(launch_expand_tiles(d_blocks, (uint32_t)pl.blocks.size(), pl.n_tiles, d_tile_block,
                               st));
     check(hipEventRecord(t_prep.ev[1], st));
@@ -395,7 +434,6 @@ int join(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint6
         uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
         unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
         check(launch_copy_u64(results, results_n, nr, st));
-        ar.release(results);
         results = nr;
         res_cap = ncap;
       }
@@ -506,7 +544,6 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
     if (method < SSJ_BM_XOR || method > SSJ_BM_NEXT) return SSJ_E_UNSUPPORTED;
     if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    keep_pool_memory();
     Arena ar(st);
     JoinCounters *ctr = ar.alloc<JoinCounters>(1);
     JoinCounters ctr_h;
@@ -517,7 +554,7 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
     sync(st);
     if (ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
     if (s->n_sets == 0) return s->n_tokens ? SSJ_E_INVALID : SSJ_OK;
-    check(launch_build_bitmaps(s->offsets, s->tokens, nullptr, s->n_sets, b_bits, method,
+    check(launch_build_bitmaps(s->offsets, s->tokens, nullptr, nullptr, s->n_sets, b_bits, method,
                                b_bits / 64, bitmaps_dev, ctr, st));
     d2h(&ctr_h, ctr, 1, st);
     sync(st);

@@ -24,12 +24,17 @@ struct JoinCounters {
   unsigned long long survivors;     // real survivors seen by verification
   unsigned long long results;       // pairs written to the result buffer
   uint32_t overflow;                // the queue filled during this filter launch
-  uint32_t tile_next;               // next tile to hand out
   uint32_t n_resume;                // resume entries written this launch
   uint32_t error;                   // validation error bits (kErr*)
   uint32_t max_size;                // largest set size seen
-  uint32_t pad[3];
+  // Tile cursors: the tile list is cut into kParts contiguous partitions, one
+  // per XCD; each cursor counts the tiles handed out from its partition.
+  // Each sits in its own 128-byte line.
+  alignas(128) uint32_t tile_next[8][32];
 };
+
+// Partitions of the tile list (one per XCD of the MI355X).
+constexpr uint32_t kParts = 8;
 
 constexpr uint32_t kErrOffsets = 1u;   // malformed offsets
 constexpr uint32_t kErrUnsorted = 2u;  // a set is not strictly increasing
@@ -90,13 +95,18 @@ hipError_t launch_unpack_keys(const unsigned long long *keys, uint64_t n, uint32
 hipError_t launch_group_starts(const uint32_t *sizes, uint64_t n, uint32_t max_size,
                                uint32_t *sstart, hipStream_t st);
 
-// Bitmaps (Alg. 3/4/5, h(t) = t mod b).  Output set x (x < n) is input set
+// Bitmaps (Alg. 3/4/5, h(t) = t mod b).  Output row x (x < n) is input set
 // perm ? perm[x] : x, written with `out_words` words (>= b/64; the extra
-// words are zero).  Also checks that every set is strictly increasing.
+// words are zero); rank is the inverse of perm (both or neither given).
+// Also checks that every set is strictly increasing.
 hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
-                                const uint32_t *perm, uint64_t n, uint32_t b_bits, int method,
+                                const uint32_t *perm, const uint32_t *rank, uint64_t n,
+                                uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
                                 hipStream_t st);
+
+// rank[perm[x]] = x
+hipError_t launch_invert_perm(const uint32_t *perm, uint64_t n, uint32_t *rank, hipStream_t st);
 
 // Token-order check only (when the caller brings bitmaps).
 hipError_t launch_check_sorted(const uint64_t *offsets, const uint32_t *tokens, uint64_t n,
