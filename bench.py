@@ -1,8 +1,9 @@
 """Benchmark: bitmap-filtered exact self-join of 1,000,000 sets at Jaccard t = 4/5.
 
 One step is one full ssj_self_join call on device-resident input: size sort,
-Bitmap-Xor build (b = 128), bitmap filter over the length band, exact
-verification, sorting and copying the pairs to host memory.  The metric is
+Bitmap-Xor build (width per row-size class, chosen by the library), bitmap
+filter over the length band, exact verification, sorting and copying the pairs
+to host memory.  The metric is
 length-band pairs per second of wall time (pairs the join accounts for, the
 paper's GPU algorithm evaluates every one of them with the bitmap filter).
 
@@ -55,9 +56,13 @@ def main():
     ap.add_argument("--workload", default="selfjoin-1m")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--q", type=int, default=5)
-    ap.add_argument("--bits", type=int, default=128)
+    ap.add_argument("--bits", type=int, default=0,
+                    help="bitmap width; 0 = automatic width per row-size class")
     ap.add_argument("--tile-cols", type=int, default=0, help="0 = the library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 3 times (reference for the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the join is measured on a single MI355X "
@@ -71,6 +76,15 @@ def main():
     import paper_1711_07295_amd as ssj
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes 3 times (read {n} and write {n} bytes per copy)")
+        return
     t0 = time.perf_counter()
     col = gen.workload(args.workload)
     log(f"generated {args.workload}: {col.n_sets} sets, {col.n_tokens} tokens in "
@@ -101,16 +115,29 @@ def main():
     band = stats[0]["band_pairs"]
     ms_per_step = total / args.steps * 1e3
     value = band / (total / args.steps)
-    # roofline of the dominant kernel (the filter): algorithmic int32 lane-ops
-    # per band pair = b/32 xor + b/32 popcount-accumulate + 1 compare
-    ops_per_pair = args.bits // 16 + 1
-    filt_s = sum(s["ms_filter"] for s in stats) / 1e3
-    launches = sum(s["filter_launches"] for s in stats)
-    achieved = band * ops_per_pair * args.steps / filt_s
+    # roofline of the dominant kernel: the filter launch of the width class
+    # with the most algorithmic work.  Per band pair the filter does b/32 xor
+    # + b/32 popcount-accumulate + 1 compare (int32 lane-ops) at the width of
+    # the pair's row class; the library reports that work per class.
+    s0 = stats[0]
+    ncls = s0["n_classes"]
+    dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
+    dom_ms = sum(s["class_ms"][dom] for s in stats) / args.steps
+    dom_launches = sum(s["filter_launches"] for s in stats) / args.steps / ncls
+    achieved = s0["class_ops"][dom] / (dom_ms / 1e3)
+    filt_ms = sum(s["ms_filter"] for s in stats) / args.steps
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
             "unit": "Top/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
-            "kernel": "k_filter", "ops_per_pair": ops_per_pair,
-            "avg_launch_ms": filt_s * 1e3 / launches}
+            "kernel": f"k_filter (b = {s0['class_bits'][dom]} class)",
+            "ops_per_launch": s0["class_ops"][dom] / dom_launches,
+            "avg_launch_ms": dom_ms / dom_launches,
+            "filter_stage": {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
+                             "frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}}
+    classes = [{"max_set_size": m, "b_bits": b, "ops": o, "ms": sum(s["class_ms"][k]
+                for s in stats) / args.steps}
+               for k, (m, b, o) in enumerate(zip(s0["class_max_size"][:ncls],
+                                                 s0["class_bits"][:ncls],
+                                                 s0["class_ops"][:ncls]))]
     line = {
         "metric": "pairs/sec (bitmap-filtered join, 1M sets, J>=0.8)",
         "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -118,7 +145,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
                    "threshold": f"{args.p}/{args.q}", "similarity": "jaccard",
-                   "b_bits": args.bits, "generator": "Bitmap-Xor",
+                   "b_bits": args.bits if args.bits else "auto", "width_classes": classes,
+                   "generator": "Bitmap-Xor",
                    "band_pairs": band, "results": stats[0]["results"],
                    "checksum": f"{col.checksum():#x}"},
         "step_ms": {"p50": statistics.median(times) * 1e3,

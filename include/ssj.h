@@ -95,8 +95,16 @@ typedef struct {
   uint64_t band_pairs;      /* pairs inside the length band (Table 2) */
   uint64_t survivors;       /* band pairs the bitmap filter kept */
   uint64_t results;         /* pairs reported */
+  uint64_t filter_ops;      /* algorithmic filter work: per band pair b/16 + 1
+                               int32 lane-ops (b/32 xor, b/32 popcount, 1 compare) */
   uint32_t filter_launches; /* filter kernel launches (1 + queue drains) */
-  uint32_t b_bits;          /* bitmap width used */
+  uint32_t b_bits;          /* bitmap width asked for (0 = automatic) */
+  uint32_t n_classes;       /* row-size classes (1 for a fixed width) */
+  uint32_t class_bits[4];   /* bitmap width of each class */
+  uint32_t class_max_size[4]; /* largest row size of each class */
+  uint64_t class_ops[4];    /* filter_ops of each class */
+  float class_ms[4];        /* filter kernel time of each class (one launch
+                               per class and queue drain) */
   float ms_total;           /* call entry to pairs in host memory */
   float ms_prepare;         /* validation, size sort, plan, bitmaps */
   float ms_filter;          /* sum of filter kernel durations */
@@ -141,10 +149,13 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
  * Eq. 2; Alg. 7 without the cutoff) prunes them, and every survivor is
  * verified exactly.
  *   s            collection (device CSR)
- *   bitmaps_dev  NULL: Bitmap-Xor bitmaps of width b_bits are built
- *                internally.  Otherwise caller-owned device bitmaps of
- *                width b_bits from any generator (caller order).
- *   b_bits       bitmap width: multiple of 64 in [64, 4096]
+ *   bitmaps_dev  NULL: Bitmap-Xor bitmaps are built internally.  Otherwise
+ *                caller-owned device bitmaps of width b_bits from any
+ *                generator (caller order).
+ *   b_bits       bitmap width: multiple of 64 in [64, 4096], or 0 for an
+ *                automatic width per class of row sizes (64, 128, 256 or
+ *                512 bits, wider for larger sets, chosen from the expected
+ *                bound of Section 3.4; bitmaps_dev must then be NULL)
  *   sim          ssj_sim; only SSJ_SIM_JACCARD is available (others
  *                return SSJ_E_UNSUPPORTED)
  *   p, q         threshold t = p / q, 1 <= p <= q (reduced internally)

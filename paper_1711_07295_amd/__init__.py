@@ -43,13 +43,20 @@ class ssj_pairs(ctypes.Structure):
 
 class ssj_stats(ctypes.Structure):
     _fields_ = [("band_pairs", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
-                ("results", ctypes.c_uint64), ("filter_launches", ctypes.c_uint32),
-                ("b_bits", ctypes.c_uint32), ("ms_total", ctypes.c_float),
+                ("results", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
+                ("filter_launches", ctypes.c_uint32), ("b_bits", ctypes.c_uint32),
+                ("n_classes", ctypes.c_uint32), ("class_bits", ctypes.c_uint32 * 4),
+                ("class_max_size", ctypes.c_uint32 * 4), ("class_ops", ctypes.c_uint64 * 4),
+                ("class_ms", ctypes.c_float * 4), ("ms_total", ctypes.c_float),
                 ("ms_prepare", ctypes.c_float), ("ms_filter", ctypes.c_float),
                 ("ms_verify", ctypes.c_float), ("ms_emit", ctypes.c_float)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
 
 
 class ssj_options(ctypes.Structure):

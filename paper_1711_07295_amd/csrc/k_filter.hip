@@ -49,10 +49,9 @@ struct Rows {
 struct Sink {
   uint2 *queue;
   JoinCounters *ctr;
-  Resume *resume_out;
   unsigned long long cap;
-  uint32_t tile;
-  uint32_t resume_cap;
+  uint32_t fail_col;   // set by the slow path when the queue fills
+  uint32_t fail_slab;
 };
 
 // popcount(x) + acc as one v_bcnt_u32_b32.  Written out so that the sum over
@@ -80,64 +79,80 @@ __device__ __forceinline__ bool keep(const Rows<W, R> &rw, const uint32_t *cb, i
   return k;
 }
 
-// Slow path: write the kept pairs of columns [j, j+U).  Returns false when
-// the queue is full (the tile is to be resumed at column j).
+// Slow path: write the kept pairs of columns [j, j+U), one (column, row
+// slab) mask at a time, each with its own queue reservation.  It is rare,
+// so it reloads the bitmaps it needs instead of keeping the fast path's
+// values alive, and it does not unroll: its registers stay few.  When a
+// reservation does not fit, its slots become sentinels, the point reached
+// (column, row slab) is left in the sink and false is returned; every mask
+// before that point has been written.
 template <int W, int R, int U, bool DIAG>
-__device__ __forceinline__ bool emit(const Rows<W, R> &rw, const int32_t (&thr)[R],
-                                               const uint32_t (&cb)[U][2 * W], uint32_t j,
-                                               const Sink &sink) {
+__device__ __forceinline__ bool emit(const uint64_t *__restrict__ bm_rows,
+                                     const uint64_t *__restrict__ bm_cols, uint32_t row0,
+                                     uint32_t row_end, const int32_t (&thr)[R], uint32_t j,
+                                     Sink &sink) {
   const uint32_t lane = threadIdx.x & 63;
-  unsigned long long m[U][R];
-  uint32_t total = 0;
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      m[u][r] = __ballot(keep<W, R, DIAG>(rw, cb[u], r, thr[r], j + u));
-      total += (uint32_t)__popcll(m[u][r]);
-    }
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&sink.ctr->queue_count, (unsigned long long)total);
-  base = rfl64(base);
-  const bool fits = base + total <= sink.cap;
   const unsigned long long below = __lanemask_lt();
-  unsigned long long off = base;
+#pragma unroll 1
+  for (uint32_t k = 0; k < (uint32_t)(U * R); ++k) {
+    const uint32_t u = k / R, r = k - (k / R) * R;
+    const uint32_t i = row0 + 64u * r + lane, col = j + u;
+    int32_t t = thr[0];
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+    for (int rr = 1; rr < R; ++rr)
+      if (r == (uint32_t)rr) t = thr[rr];
+    bool kp = false;
+    if (i < row_end) {
+      const uint32_t *rb = reinterpret_cast<const uint32_t *>(bm_rows + (size_t)i * W);
+      const uint32_t *cbp = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)col * W);
+      int32_t h = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if ((m[u][r] >> lane) & 1ull) {
-        unsigned long long pos = off + (unsigned long long)__popcll(m[u][r] & below);
-        if (pos < sink.cap)
-          sink.queue[pos] = fits ? make_uint2(rw.idx[r], j + u) : make_uint2(kSentinel, kSentinel);
-      }
-      off += (unsigned long long)__popcll(m[u][r]);
+      for (int e = 0; e < 2 * W; ++e) h += __builtin_popcount(rb[e] ^ cbp[e]);
+      kp = h <= t && (!DIAG || col < i);
     }
-  if (!fits) {
-    if (lane == 0) {
-      atomicOr(&sink.ctr->overflow, 1u);
-      uint32_t k = atomicAdd(&sink.ctr->n_resume, 1u);
-      Resume rs;
-      rs.tile = sink.tile;
-      rs.col = j;
-      if (k < sink.resume_cap) sink.resume_out[k] = rs;
+    const unsigned long long m = __ballot(kp);
+    if (!m) continue;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&sink.ctr->queue_count, (unsigned long long)cnt);
+    base = rfl64(base);
+    const bool fits = base + cnt <= sink.cap;
+    if (kp) {
+      const unsigned long long pos = base + (unsigned long long)__popcll(m & below);
+      if (pos < sink.cap)
+        sink.queue[pos] = fits ? make_uint2(i, col) : make_uint2(kSentinel, kSentinel);
     }
-    return false;
+    if (!fits) {
+      // the wave's main loop records (tile, column, slab) for resumption
+      sink.fail_col = col;
+      sink.fail_slab = r;
+      return false;
+    }
   }
   return true;
 }
 
+// Column bitmaps are read through the constant address space: they are not
+// written while the kernel runs, and uniform loads from that space always
+// become scalar loads (s_load), whatever the slow path stores.
+typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
+
+__device__ __forceinline__ const_u32_ptr as_const(const uint64_t *p) {
+  return (const_u32_ptr)(p);
+}
+
 // Columns [j, g1) of one size group.
 template <int W, int R, int U, bool DIAG>
-__device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
-                                      const int32_t (&thr)[R], uint32_t j, uint32_t g1,
-                                      const Sink &sink) {
+__device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_rows,
+                                      const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
+                                      uint32_t row0, uint32_t row_end, const int32_t (&thr)[R],
+                                      uint32_t j, uint32_t g1, Sink &sink) {
   // Scalar loads may return out of order, so a wave can only wait for all
   // of them; the next step's columns are therefore requested right after the
   // wait for the current step and arrive while the current step computes.
   uint32_t nb[U][2 * W];
   if (j + U <= g1) {
-    const uint32_t *p = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)j * W);
+    const_u32_ptr p = as_const(bm_cols + (size_t)j * W);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -150,7 +165,7 @@ __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_cols, cons
 #pragma unroll
       for (int e = 0; e < 2 * W; ++e) cb[u][e] = nb[u][e];
     if (j + 2 * U <= g1) {
-      const uint32_t *p = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)(j + U) * W);
+      const_u32_ptr p = as_const(bm_cols + (size_t)(j + U) * W);
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -162,24 +177,91 @@ __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_cols, cons
 #pragma unroll
       for (int r = 0; r < R; ++r) any |= __ballot(keep<W, R, DIAG>(rw, cb[u], r, thr[r], j + u));
     if (any) {
-      if (!emit<W, R, U, DIAG>(rw, thr, cb, j, sink)) return false;
+      if (!emit<W, R, U, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink)) return false;
     }
   }
   for (; j < g1; ++j) {
     uint32_t cb[1][2 * W];
-    const uint32_t *p = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)j * W);
+    const_u32_ptr p = as_const(bm_cols + (size_t)j * W);
 #pragma unroll
     for (int e = 0; e < 2 * W; ++e) cb[0][e] = p[e];
     unsigned long long any = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) any |= __ballot(keep<W, R, DIAG>(rw, cb[0], r, thr[r], j));
     if (any) {
-      if (!emit<W, R, 1, DIAG>(rw, thr, cb, j, sink)) return false;
+      if (!emit<W, R, 1, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink)) return false;
     }
   }
   return true;
 }
 
+// One tile: rows [row0, row_end) of a row block (at most 64*R of them, R per
+// lane, interleaved by 64), columns [c0, c1).  Returns false when the queue
+// filled (a resume point has been recorded).
+template <int W, int R, int U>
+__device__ __forceinline__ bool run_tile(
+    const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
+    const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
+    const uint32_t *__restrict__ sstart_cols, const int32_t *__restrict__ slack,
+    const uint32_t *__restrict__ cmin, const uint32_t *__restrict__ cmax, uint32_t row0,
+    uint32_t row_end, uint32_t c0, uint32_t c1, bool diag, uint32_t first_slab, Sink &sink) {
+  const uint32_t lane = threadIdx.x & 63;
+  Rows<W, R> rw;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = row0 + 64u * r + lane;
+    rw.idx[r] = i;
+    if (i < row_end) {
+      const uint32_t a = size_rows[i];
+      rw.size[r] = a;
+      rw.cmn[r] = cmin[a];
+      rw.cmx[r] = cmax[a];
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(bm_rows + (size_t)i * W);
+#pragma unroll
+      for (int e = 0; e < 2 * W; ++e) rw.bits[r][e] = src[e];
+    } else {
+      rw.size[r] = 0;
+      rw.cmn[r] = 0xFFFFFFFFu;
+      rw.cmx[r] = 0;
+#pragma unroll
+      for (int e = 0; e < 2 * W; ++e) rw.bits[r][e] = 0;
+    }
+  }
+  uint32_t j = c0;
+  while (j < c1) {
+    const uint32_t c = rfl(size_cols[j]);
+    const uint32_t g1 = min(max(rfl(sstart_cols[c + 1]), j + 1), c1);  // always advances
+    int32_t thr[R];
+    bool any_ok = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in_band = c >= rw.cmn[r] && c <= rw.cmx[r];
+      thr[r] = in_band ? slack[rw.size[r] + c] : -1;
+      any_ok |= in_band;
+    }
+    // resumed inside column j: its slabs below first_slab are already queued,
+    // so column j runs alone with those slabs masked off
+    const uint32_t gend = first_slab ? j + 1 : g1;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if ((uint32_t)r < first_slab) thr[r] = -1;
+    first_slab = 0;
+    if (__ballot(any_ok)) {
+      const bool ok =
+          diag ? sweep<W, R, U, true>(bm_rows, bm_cols, rw, row0, row_end, thr, j, gend, sink)
+               : sweep<W, R, U, false>(bm_rows, bm_cols, rw, row0, row_end, thr, j, gend, sink);
+      if (!ok) return false;
+    }
+    j = gend;
+  }
+  return true;
+}
+
+// Persistent filter for one bitmap width (W words, R rows per lane, U
+// columns per step) over the tiles [cfg.tile_lo, cfg.tile_hi) of the plan.
+// Waves first take the resume entries of a previous launch that fall in
+// that range (entry k goes to wave k), then tiles from the partitioned
+// cursors, until the range is exhausted or the queue has filled.
 template <int W, int R, int U>
 __global__ __launch_bounds__(kBlock) void k_filter(
     const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
@@ -194,31 +276,39 @@ __global__ __launch_bounds__(kBlock) void k_filter(
   Sink sink;
   sink.queue = queue;
   sink.ctr = ctr;
-  sink.resume_out = resume_out;
   sink.cap = cfg.cap;
-  sink.resume_cap = cfg.resume_cap;
+  sink.fail_col = 0;
+  sink.fail_slab = 0;
 
-  bool resumed = wave < cfg.n_resume_in && wave < cfg.resume_cap;
-  uint32_t t = 0, col = 0;
-  if (resumed) {
+  bool resumed = false;
+  uint32_t t = 0, col = 0, slab = 0;
+  if (wave < cfg.n_resume_in && wave < cfg.resume_cap) {
     t = rfl(resume_in[wave].tile);
     col = rfl(resume_in[wave].col);
+    slab = rfl(resume_in[wave].slab);
+    resumed = t >= cfg.tile_lo && t < cfg.tile_hi;
   }
+  const uint32_t n_tiles = cfg.tile_hi - cfg.tile_lo;
+  uint32_t *cursors = &ctr->tile_next[cfg.cls][0][0];
   // Workgroups are dispatched to the XCDs round-robin: start in this XCD's
-  // partition of the tile list, move on to the others when it runs dry.
+  // partition of the tile range, move on to the others when it runs dry.
   uint32_t part = blockIdx.x % kParts, parts_left = kParts;
   for (;;) {
     if (!resumed) {
       if (__hip_atomic_load(&ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
       bool got = false;
       while (parts_left) {
-        const uint32_t p0 = (uint32_t)(((uint64_t)cfg.n_tiles * part) / kParts);
-        const uint32_t p1 = (uint32_t)(((uint64_t)cfg.n_tiles * (part + 1)) / kParts);
-        uint32_t tt = 0;
-        if (lane == 0) tt = atomicAdd(&ctr->tile_next[part][0], 1u);
+        const uint32_t p0 = (uint32_t)(((uint64_t)n_tiles * part) / kParts);
+        const uint32_t p1 = (uint32_t)(((uint64_t)n_tiles * (part + 1)) / kParts);
+        // a relaxed read first: exhausted partitions cost no atomic
+        uint32_t tt = p1 - p0;
+        if (lane == 0 &&
+            __hip_atomic_load(&cursors[part * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                p1 - p0)
+          tt = atomicAdd(&cursors[part * 32], 1u);
         tt = rfl(tt);
         if (tt < p1 - p0) {
-          t = p0 + tt;
+          t = cfg.tile_lo + p0 + tt;
           got = true;
           break;
         }
@@ -231,6 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(
     const uint32_t b = rfl(tile_block[t]);
     if (b >= cfg.n_blocks) return;
     const uint32_t row0 = rfl(blocks[b].row0);
+    const uint32_t row_end = rfl(blocks[b].row_end);
     const uint32_t cbeg = rfl(blocks[b].col_begin);
     const uint32_t cend = rfl(blocks[b].col_end);
     const uint32_t k = t - rfl(blocks[b].tile_begin);
@@ -250,71 +341,41 @@ __global__ __launch_bounds__(kBlock) void k_filter(
       c0 = cbeg + k * cfg.tile_cols;
       c1 = min(c0 + cfg.tile_cols, cend);
     }
-    if (resumed) c0 = col;
+    uint32_t first_slab = 0;
+    if (resumed) {
+      c0 = col;
+      first_slab = slab;
+    }
     resumed = false;
-    sink.tile = t;
-
-    // the wave's rows
-    Rows<W, R> rw;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = row0 + 64u * r + lane;
-      rw.idx[r] = i;
-      if (i < cfg.n_rows) {
-        const uint32_t a = size_rows[i];
-        rw.size[r] = a;
-        rw.cmn[r] = cmin[a];
-        rw.cmx[r] = cmax[a];
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(bm_rows + (size_t)i * W);
-#pragma unroll
-        for (int e = 0; e < 2 * W; ++e) rw.bits[r][e] = src[e];
-      } else {
-        rw.size[r] = 0;
-        rw.cmn[r] = 0xFFFFFFFFu;
-        rw.cmx[r] = 0;
-#pragma unroll
-        for (int e = 0; e < 2 * W; ++e) rw.bits[r][e] = 0;
+    if (!run_tile<W, R, U>(bm_rows, bm_cols, size_rows, size_cols, sstart_cols, slack, cmin,
+                           cmax, row0, min(row_end, cfg.n_rows), c0, c1, diag, first_slab,
+                           sink)) {
+      // the queue is full: record where this tile resumes, and stop
+      const uint32_t fcol = rfl(sink.fail_col), fslab = rfl(sink.fail_slab);
+      if (lane == 0) {
+        atomicOr(&ctr->overflow, 1u);
+        const uint32_t q = atomicAdd(&ctr->n_resume, 1u);
+        Resume rs;
+        rs.tile = t;
+        rs.col = fcol;
+        rs.slab = fslab;
+        rs.pad = 0;
+        if (q < cfg.resume_cap) resume_out[q] = rs;
       }
+      return;
     }
-
-    bool ok = true;
-    uint32_t j = c0;
-    while (j < c1) {
-      const uint32_t c = rfl(size_cols[j]);
-      const uint32_t g1 = min(max(rfl(sstart_cols[c + 1]), j + 1), c1);  // always advances
-      int32_t thr[R];
-      bool any_ok = false;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const bool in_band = c >= rw.cmn[r] && c <= rw.cmx[r];
-        thr[r] = in_band ? slack[rw.size[r] + c] : -1;
-        any_ok |= in_band;
-      }
-      if (__ballot(any_ok)) {
-        ok = diag ? sweep<W, R, U, true>(bm_cols, rw, thr, j, g1, sink)
-                  : sweep<W, R, U, false>(bm_cols, rw, thr, j, g1, sink);
-        if (!ok) break;
-      }
-      j = g1;
-    }
-    if (!ok) return;
   }
 }
 
 template <int W, int R, int U>
-hipError_t launch_w(dim3 grid, hipStream_t st, const uint64_t *bm_rows, const uint64_t *bm_cols,
-                    const uint32_t *size_rows, const uint32_t *size_cols,
-                    const uint32_t *sstart_cols, const int32_t *slack, const uint32_t *cmin,
-                    const uint32_t *cmax, const RowBlock *blocks, const uint32_t *tile_block,
-                    uint2 *queue, JoinCounters *ctr, const Resume *resume_in,
-                    Resume *resume_out, FilterConfig cfg) {
-  hipLaunchKernelGGL((k_filter<W, R, U>), grid, dim3(kBlock), 0, st, bm_rows, bm_cols, size_rows,
-                     size_cols, sstart_cols, slack, cmin, cmax, blocks, tile_block, queue, ctr,
-                     resume_in, resume_out, cfg);
+hipError_t launch_shape(dim3 grid, hipStream_t st, const FilterArgs &a) {
+  hipLaunchKernelGGL((k_filter<W, R, U>), grid, dim3(kBlock), 0, st, a.bm_rows, a.bm_cols,
+                     a.size_rows, a.size_cols, a.sstart_cols, a.slack, a.cmin, a.cmax, a.blocks,
+                     a.tile_block, a.queue, a.ctr, a.resume_in, a.resume_out, a.cfg);
   return hipGetLastError();
 }
 
-// (padded words, rows per lane, columns per step)
+// Fixed-width kernels: (padded words, rows per lane, columns per step)
 #define SSJ_FILTER_SHAPES(X) \
   X(1, 2, 8)                 \
   X(2, 2, 4)                 \
@@ -346,10 +407,10 @@ uint32_t filter_padded_words(uint32_t words) {
 
 FilterShape filter_shape(uint32_t padded_words) {
   FilterShape s{0, 0, 0};
-#define X(w, r, u)       \
-  if (padded_words == (w)) { \
-    s.words = (w);       \
-    s.rows = 64 * (r);   \
+#define X(w, r, u)            \
+  if (padded_words == (w)) {  \
+    s.words = (w);            \
+    s.rows = 64 * (r);        \
     s.batch = 64 * (r) * (u); \
   }
   SSJ_FILTER_SHAPES(X)
@@ -366,19 +427,10 @@ int filter_grid_blocks() {
   return cus * 8;  // 32 waves per CU
 }
 
-hipError_t launch_filter(uint32_t padded_words, const uint64_t *bm_rows, const uint64_t *bm_cols,
-                         const uint32_t *size_rows, const uint32_t *size_cols,
-                         const uint32_t *sstart_cols, const int32_t *slack,
-                         const uint32_t *cmin, const uint32_t *cmax, const RowBlock *blocks,
-                         const uint32_t *tile_block, uint2 *queue, JoinCounters *ctr,
-                         const Resume *resume_in, Resume *resume_out, FilterConfig cfg,
-                         hipStream_t st) {
+hipError_t launch_filter(uint32_t padded_words, const FilterArgs &a, hipStream_t st) {
   dim3 grid(filter_grid_blocks());
-#define X(w, r, u)                                                                           \
-  if (padded_words == (w))                                                                   \
-    return launch_w<w, r, u>(grid, st, bm_rows, bm_cols, size_rows, size_cols, sstart_cols, \
-                             slack, cmin, cmax, blocks, tile_block, queue, ctr, resume_in,   \
-                             resume_out, cfg);
+#define X(w, r, u) \
+  if (padded_words == (w)) return launch_shape<w, r, u>(grid, st, a);
   SSJ_FILTER_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

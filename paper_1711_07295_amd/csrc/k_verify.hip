@@ -16,6 +16,55 @@
 namespace ssj {
 namespace {
 
+constexpr int kWin = 8;  // tokens per merge window
+
+// Load tokens [at, at + kWin) of a set of n tokens; slots past the end are
+// marked invalid.  The loads are independent, so a refill costs one round trip.
+__host__ __device__ __forceinline__ void load_window(const uint32_t *__restrict__ t, uint32_t n,
+                                            uint32_t at, uint32_t (&w)[kWin]) {
+#pragma unroll
+  for (int k = 0; k < kWin; ++k) w[k] = at + k < n ? t[at + k] : 0u;
+}
+
+// |r n s| >= need for two strictly increasing token lists, by a windowed
+// merge: count the common tokens of the current windows, then drop the
+// window whose last token is smaller (both when equal).  A common token sits
+// in both current windows at some step and leaves with the dropped window,
+// so it is counted once.  Stops as soon as the tokens left cannot reach need.
+__host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restrict__ rp, uint32_t a,
+                                                const uint32_t *__restrict__ sp, uint32_t c,
+                                                uint32_t need) {
+  uint32_t ia = 0, ic = 0, o = 0;
+  uint32_t rw[kWin], sw[kWin];
+  load_window(rp, a, 0, rw);
+  load_window(sp, c, 0, sw);
+  while (ia < a && ic < c) {
+    if (o + min(a - ia, c - ic) < need) return false;
+    const uint32_t nr = min(a - ia, (uint32_t)kWin), ns = min(c - ic, (uint32_t)kWin);
+#pragma unroll
+    for (int x = 0; x < kWin; ++x)
+#pragma unroll
+      for (int y = 0; y < kWin; ++y)
+        o += ((uint32_t)x < nr && (uint32_t)y < ns && rw[x] == sw[y]) ? 1u : 0u;
+    // last valid token of each window
+    uint32_t rmax = rw[0], smax = sw[0];
+#pragma unroll
+    for (int k = 1; k < kWin; ++k) {
+      if ((uint32_t)k < nr) rmax = rw[k];
+      if ((uint32_t)k < ns) smax = sw[k];
+    }
+    if (rmax <= smax) {
+      ia += nr;
+      load_window(rp, a, ia, rw);
+    }
+    if (smax <= rmax) {
+      ic += ns;
+      load_window(sp, c, ic, sw);
+    }
+  }
+  return o >= need;
+}
+
 __global__ __launch_bounds__(kBlock) void k_verify(
     const uint2 *__restrict__ queue, unsigned long long cap,
     const uint64_t *__restrict__ off_rows, const uint32_t *__restrict__ tok_rows,
@@ -48,29 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_verify(
         if (survivors_only) {
           hit = true;
         } else {
-          const uint32_t need = omin[a + c];
-          const uint32_t *rp = tok_rows + r0;
-          const uint32_t *sp = tok_cols + s0;
-          uint32_t ia = 0, ic = 0, o = 0;
-          uint32_t u = a ? rp[0] : 0, v = c ? sp[0] : 0;
-          while (ia < a && ic < c) {
-            const uint32_t rest = min(a - ia, c - ic);
-            if (o + rest < need) break;
-            if (u == v) {
-              ++o;
-              ++ia;
-              ++ic;
-              if (ia < a) u = rp[ia];
-              if (ic < c) v = sp[ic];
-            } else if (u < v) {
-              ++ia;
-              if (ia < a) u = rp[ia];
-            } else {
-              ++ic;
-              if (ic < c) v = sp[ic];
-            }
-          }
-          hit = a != 0 && c != 0 && o >= need;
+          hit = a != 0 && c != 0 && overlap_reaches(tok_rows + r0, a, tok_cols + s0, c,
+                                                   omin[a + c]);
         }
         if (hit) {
           if (self) {

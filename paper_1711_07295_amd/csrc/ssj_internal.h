@@ -27,35 +27,46 @@ struct JoinCounters {
   uint32_t n_resume;                // resume entries written this launch
   uint32_t error;                   // validation error bits (kErr*)
   uint32_t max_size;                // largest set size seen
-  // Tile cursors: the tile list is cut into kParts contiguous partitions, one
-  // per XCD; each cursor counts the tiles handed out from its partition.
-  // Each sits in its own 128-byte line.
-  alignas(128) uint32_t tile_next[8][32];
+  // Tile cursors: each width class's tile range is cut into kParts
+  // contiguous partitions, one per XCD; each cursor counts the tiles handed
+  // out from its partition.  Each sits in its own 128-byte line.
+  alignas(128) uint32_t tile_next[4][8][32];
 };
 
-// Partitions of the tile list (one per XCD of the MI355X).
+// Partitions of a tile range (one per XCD of the MI355X).
 constexpr uint32_t kParts = 8;
+// Width classes of one join (one filter launch each).
+constexpr uint32_t kMaxClasses = 4;
 
 constexpr uint32_t kErrOffsets = 1u;   // malformed offsets
 constexpr uint32_t kErrUnsorted = 2u;  // a set is not strictly increasing
 constexpr uint32_t kErrTooBig = 4u;    // a set has 2^32 or more tokens
+constexpr uint32_t kErrPlan = 8u;      // a row block with no filter path (internal error)
 
-// One row block of the filter's tile plan: 64*R consecutive rows of the
-// size-ordered row collection and the column range they are compared with.
+// One row block of the filter's tile plan: up to 64*R consecutive rows
+// [row0, row_end) of the size-ordered row collection, all of one bitmap
+// width (`words` 64-bit words), and the column range they are compared with.
 // Self-join: columns [col_begin, row0) in interior tiles of tile_cols
-// columns, then one diagonal tile [row0, row_end) where only j < i counts.
+// columns, then one diagonal tile [row0, col_end) where only j < i counts.
 // R-S join: columns [col_begin, col_end) in tiles of tile_cols columns.
 struct RowBlock {
   uint32_t row0;
+  uint32_t row_end;
   uint32_t col_begin;
   uint32_t col_end;
   uint32_t tile_begin;
+  uint32_t words;
+  uint32_t pad[2];
 };
 
-// A tile to resume after a queue drain: (tile index, first column).
+// A tile to resume after a queue drain: tile index, first column, and the
+// first slab of rows (rows r*64 .. r*64+63 of the block) of that column
+// still to be written.
 struct Resume {
   uint32_t tile;
   uint32_t col;
+  uint32_t slab;
+  uint32_t pad;
 };
 
 // Filter launch arguments that are not hot pointers.
@@ -67,8 +78,12 @@ struct FilterConfig {
   uint32_t self;          // 1: self-join (triangle j < i in diagonal tiles)
   uint32_t n_resume_in;
   uint32_t n_blocks;
-  uint32_t resume_cap;       // entries of the resume buffers
+  uint32_t resume_cap;    // entries of the resume buffers
   unsigned long long cap; // survivor queue capacity (entries)
+  uint32_t tile_lo;       // this launch's tile range [tile_lo, tile_hi)
+  uint32_t tile_hi;
+  uint32_t cls;           // width class (selects the tile cursors)
+  uint32_t pad;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -132,13 +147,26 @@ uint32_t filter_padded_words(uint32_t words);
 FilterShape filter_shape(uint32_t padded_words);
 int filter_grid_blocks();
 
-hipError_t launch_filter(uint32_t padded_words, const uint64_t *bm_rows, const uint64_t *bm_cols,
-                         const uint32_t *size_rows, const uint32_t *size_cols,
-                         const uint32_t *sstart_cols, const int32_t *slack,
-                         const uint32_t *cmin, const uint32_t *cmax, const RowBlock *blocks,
-                         const uint32_t *tile_block, uint2 *queue, JoinCounters *ctr,
-                         const Resume *resume_in, Resume *resume_out, FilterConfig cfg,
-                         hipStream_t st);
+struct FilterArgs {
+  const uint64_t *bm_rows;
+  const uint64_t *bm_cols;
+  const uint32_t *size_rows;
+  const uint32_t *size_cols;
+  const uint32_t *sstart_cols;
+  const int32_t *slack;
+  const uint32_t *cmin;
+  const uint32_t *cmax;
+  const RowBlock *blocks;
+  const uint32_t *tile_block;
+  uint2 *queue;
+  JoinCounters *ctr;
+  const Resume *resume_in;
+  Resume *resume_out;
+  FilterConfig cfg;
+};
+
+// One launch for the width padded_words (from filter_padded_words).
+hipError_t launch_filter(uint32_t padded_words, const FilterArgs &args, hipStream_t st);
 
 // Verification of the queued survivors (sorted merge, Table 1 predicate)
 // into 64-bit result keys (caller indices; self-join keys are (min, max)).

@@ -57,7 +57,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ssj.ssj_pair) == 8
     assert ctypes.sizeof(ssj.ssj_pairs) == 16
     assert ctypes.sizeof(ssj.ssj_options) == 16
-    assert ctypes.sizeof(ssj.ssj_stats) == 8 * 3 + 4 * 2 + 4 * 5 + 4  # padded to 8
+    assert ctypes.sizeof(ssj.ssj_stats) == 8 * 4 + 4 * 3 + 4 * 8 + 4 + 8 * 4 + 4 * 4 + 4 * 5 + 4
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -192,3 +192,66 @@ def test_selfjoin_1m_sampled():
     want = oracle.self_join_rows(c.offsets, c.tokens, rows, 4, 5)
     mask = np.isin(got[:, 0], rows) | np.isin(got[:, 1], rows)
     assert np.array_equal(got[mask], want)
+
+
+@pytest.mark.parametrize("pq", [(1, 2), (7, 10), (4, 5), (9, 10)])
+def test_automatic_width_classes_match_oracle(pq):
+    """b_bits = 0: row-size classes with their own widths, exact result."""
+    p, q = pq
+    c = gen.generate(n_sets=4000, universe=3000, zipf_s=1.0, size_dist=gen.SIZE_LOGNORMAL,
+                     size_a=40.0, size_b=1.0, size_lo=1, size_hi=600, planted_frac=0.2,
+                     seed=300 + p)
+    want = oracle.self_join(c.offsets, c.tokens, p, q)
+    got, st = ssj.ssj_self_join(_dev(c), p, q, b_bits=0)
+    assert np.array_equal(got, want)
+    assert st["b_bits"] == 0 and st["n_classes"] >= 2
+    assert st["band_pairs"] == oracle.band_pairs(c.sizes(), p, q)
+    bits = st["class_bits"][:st["n_classes"]]
+    assert bits == sorted(bits) and set(bits) <= {64, 128, 256, 512}
+    # the filter's algorithmic work lies between the narrowest and widest class
+    assert st["band_pairs"] * (bits[0] // 16 + 1) <= st["filter_ops"]
+    assert st["filter_ops"] <= st["band_pairs"] * (bits[-1] // 16 + 1)
+    r, s = _ragged(51, n=700, universe=900, hi=300), _ragged(52, n=900, universe=900, hi=300)
+    want = oracle.rs_join(r.offsets, r.tokens, s.offsets, s.tokens, p, q)
+    got, _ = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=0)
+    assert np.array_equal(got, want)
+
+
+def test_automatic_width_rejects_caller_bitmaps():
+    c = _ragged(61, n=100)
+    d = _dev(c)
+    bm = ssj.ssj_build_bitmaps(d, 64)
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_self_join(d, 1, 2, b_bits=0, bitmaps=bm)
+    assert e.value.status == ssj.SSJ_E_INVALID
+
+
+def test_selfjoin_1m_sampled_automatic_width():
+    c = gen.workload("selfjoin-1m")
+    got, st = ssj.ssj_self_join(_dev(c), 4, 5, b_bits=0)
+    fixed, _ = ssj.ssj_self_join(_dev(c), 4, 5, b_bits=128)
+    assert np.array_equal(got, fixed)
+    assert st["n_classes"] >= 2
+    rng = np.random.default_rng(77)
+    rows = rng.choice(c.n_sets, size=200, replace=False)
+    want = oracle.self_join_rows(c.offsets, c.tokens, rows, 4, 5)
+    mask = np.isin(got[:, 0], rows) | np.isin(got[:, 1], rows)
+    assert np.array_equal(got[mask], want)
+
+
+def test_selfjoin_10m_row_sample():
+    """The 10,000,000-set workload at t = 4/5 (automatic widths): every pair
+    that involves one of 40 sampled sets matches the oracle, and a sample of
+    the reported pairs passes the oracle's check."""
+    c = gen.workload("selfjoin-10m")
+    got, st = ssj.ssj_self_join(_dev(c), 4, 5, b_bits=0)
+    assert st["band_pairs"] == oracle.band_pairs(c.sizes(), 4, 5)
+    assert len(got) > 10_000 and np.all(got[:, 0] < got[:, 1])
+    rng = np.random.default_rng(10)
+    pick = got[rng.choice(len(got), size=min(len(got), 200_000), replace=False)]
+    assert oracle.check_pairs(c.offsets, c.tokens, c.offsets, c.tokens, pick, 4, 5).all()
+    rows = np.unique(np.concatenate([rng.choice(c.n_sets, size=30, replace=False),
+                                     got[rng.choice(len(got), 10, replace=False), 1]]))
+    want = oracle.self_join_rows(c.offsets, c.tokens, rows, 4, 5)
+    mask = np.isin(got[:, 0], rows) | np.isin(got[:, 1], rows)
+    assert np.array_equal(got[mask], want)
