@@ -7,6 +7,13 @@ to host memory.  The metric is
 length-band pairs per second of wall time (pairs the join accounts for, the
 paper's GPU algorithm evaluates every one of them with the bitmap filter).
 
+Other modes (not the default):
+  --mode batch   256 uneven self-join instances: one ssj_self_join_batch call
+                 per step, against the same instances as sequential calls;
+  --mode serve   R-S query batches against a resident 5,000,000-set index
+                 under continuous batching, Poisson arrivals at several loads:
+                 p50/p99 latency, batches/s and pairs/s.
+
 Prints one JSON line on stdout.  Details go to stderr.
 """
 from __future__ import annotations
@@ -51,6 +58,12 @@ def cpu_baseline(col, p, q, fraction=0.005):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", choices=("selfjoin", "batch", "serve"), default="selfjoin")
+    ap.add_argument("--instances", type=int, default=256, help="batch mode: instances")
+    ap.add_argument("--serve-batches", type=int, default=2000,
+                    help="serve mode: measured batches per load (plus 100 warm-up)")
+    ap.add_argument("--resident", type=int, default=5_000_000,
+                    help="serve mode: sets in the resident index")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="selfjoin-1m")
@@ -76,6 +89,10 @@ def main():
     import paper_1711_07295_amd as ssj
 
     torch.cuda.set_device(0)
+    if args.mode == "batch":
+        return run_batch(args)
+    if args.mode == "serve":
+        return run_serve(args)
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
         src = torch.ones(n // 8, dtype=torch.int64, device="cuda")
@@ -160,6 +177,162 @@ def main():
         log("cpu baseline: oracle on a 0.5% row sample ...")
         line["cpu_baseline"] = cpu_baseline(col, args.p, args.q)
         log(f"cpu baseline: {line['cpu_baseline']}")
+    print(json.dumps(line), flush=True)
+
+
+def roofline_of(stats_list, steps):
+    """Roofline entry of the dominant filter launch (the width class with the
+    most algorithmic work), from the library's per-class event timings."""
+    s0 = stats_list[0]
+    ncls = s0["n_classes"]
+    dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
+    dom_ms = sum(s["class_ms"][dom] for s in stats_list) / steps
+    launches = sum(s["filter_launches"] for s in stats_list) / steps / ncls
+    achieved = s0["class_ops"][dom] / (dom_ms / 1e3)
+    filt_ms = sum(s["ms_filter"] for s in stats_list) / steps
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
+            "unit": "Top/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
+            "kernel": f"k_filter (b = {s0['class_bits'][dom]} class)",
+            "ops_per_launch": s0["class_ops"][dom] / launches,
+            "avg_launch_ms": dom_ms / launches,
+            "filter_stage": {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
+                             "frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}}
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1711_07295_amd as ssj
+
+    t0 = time.perf_counter()
+    inst = gen.batched_instances(args.instances)
+    n_sets = sum(c.n_sets for c, _ in inst)
+    n_tok = sum(c.n_tokens for c, _ in inst)
+    log(f"generated {len(inst)} instances: {n_sets} sets, {n_tok} tokens in "
+        f"{time.perf_counter() - t0:.1f} s")
+    devs = [ssj.to_device(c.offsets, c.tokens) for c, _ in inst]
+    ps, qs = [t[0] for _, t in inst], [t[1] for _, t in inst]
+    torch.cuda.synchronize()
+
+    def batched():
+        return ssj.ssj_self_join_batch(devs, ps, qs, b_bits=args.bits, tile_cols=args.tile_cols)
+
+    def sequential():
+        band, res = 0, 0
+        for d, p, q in zip(devs, ps, qs):
+            _, st = ssj.ssj_self_join(d, p, q, b_bits=args.bits, tile_cols=args.tile_cols)
+            band += st["band_pairs"]
+            res += st["results"]
+        return band, res
+
+    for w in range(args.warmup):
+        got, st = batched()
+        log(f"warmup {w}: {st['results']} pairs, {st['ms_total']:.2f} ms")
+    sequential()
+    torch.cuda.synchronize()
+    times, stats = [], []
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        got, st = batched()
+        times.append(time.perf_counter() - t1)
+        stats.append(st)
+        log(f"batched step {k}: {times[-1] * 1e3:.2f} ms  filter {st['ms_filter']:.2f}  "
+            f"verify {st['ms_verify']:.2f}  prepare {st['ms_prepare']:.2f}  "
+            f"emit {st['ms_emit']:.2f}  results {st['results']}")
+    torch.cuda.synchronize()
+    seq_times = []
+    for k in range(max(1, args.steps // 2)):
+        t1 = time.perf_counter()
+        band_seq, res_seq = sequential()
+        seq_times.append(time.perf_counter() - t1)
+        log(f"sequential step {k}: {seq_times[-1] * 1e3:.2f} ms")
+    band = stats[0]["band_pairs"]
+    assert band == band_seq and stats[0]["results"] == res_seq
+    ms = statistics.mean(times) * 1e3
+    seq_ms = statistics.mean(seq_times) * 1e3
+    line = {
+        "metric": "pairs/sec (batched bitmap-filtered self-joins)",
+        "value": band / (ms / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched-{len(inst)}", "instances": len(inst),
+                   "n_sets": n_sets, "n_tokens": n_tok,
+                   "b_bits": args.bits if args.bits else "auto", "band_pairs": band,
+                   "results": stats[0]["results"]},
+        "sequential": {"ms_per_step": seq_ms, "value": band / (seq_ms / 1e3),
+                       "calls": len(inst)},
+        "speedup_vs_sequential": seq_ms / ms,
+        "step_ms": {"p50": statistics.median(times) * 1e3,
+                    "p99": float(np.percentile(np.array(times), 99)) * 1e3},
+        "stage_ms": {k: statistics.mean(s[k] for s in stats)
+                     for k in ("ms_prepare", "ms_filter", "ms_verify", "ms_emit")},
+        "roofline": roofline_of(stats, args.steps),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args):
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1711_07295_amd as ssj
+    from paper_1711_07295_amd.serve import ContinuousBatcher, poisson_arrivals
+
+    warm = 100
+    t0 = time.perf_counter()
+    sw = gen.served_workload(warm + args.serve_batches, resident_sets=args.resident)
+    log(f"generated resident {sw.resident.n_sets} sets and {len(sw.batches)} query batches "
+        f"({sum(b.n_sets for b in sw.batches)} sets) in {time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
+    idx = ssj.Index(ssj.to_device(sw.resident.offsets, sw.resident.tokens), b_bits=args.bits)
+    torch.cuda.synchronize()
+    log(f"index built in {time.perf_counter() - t1:.2f} s")
+    srv = ContinuousBatcher(idx)
+    batches, thr = sw.batches, sw.thresholds
+    # plain service rate: one batch per call, back to back
+    n_plain = min(300, len(batches))
+    srv.run(batches[:warm], thr[:warm], np.zeros(warm))
+    t1 = time.perf_counter()
+    for k in range(n_plain):
+        srv.run([batches[k]], [thr[k]], [0.0])
+    mu = n_plain / (time.perf_counter() - t1)
+    log(f"plain service rate: {mu:.1f} batches/s")
+    loads = []
+    for rho in (0.5, 0.8, 0.95, 1.2):
+        arr = poisson_arrivals(len(batches), rho * mu, seed=int(rho * 1000))
+        r = srv.run(batches, thr, arr)
+        m = slice(warm, None)  # measured batches
+        lat, wait = r.latency_s[m] * 1e3, r.wait_s[m] * 1e3
+        span = float(arr[-1] - arr[warm]) if len(arr) > warm + 1 else r.wall_s
+        ent = {"rho": rho, "arrival_rate": rho * mu, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+               "wait_p50_ms": float(np.percentile(wait, 50)),
+               "wait_p99_ms": float(np.percentile(wait, 99)),
+               "batches_per_s": len(batches) / r.wall_s, "pairs_per_s": r.band_pairs / r.wall_s,
+               "calls": r.calls, "mean_batches_per_call": float(r.batches_per_call.mean()),
+               "results": r.results, "measured_span_s": span}
+        loads.append(ent)
+        log(f"rho {rho}: {ent}")
+    idx.close()
+    head = [e for e in loads if e["rho"] == 0.95][0]
+    line = {
+        "metric": "pairs/sec + p50/p99 query latency (served R-S joins, continuous batching)",
+        "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.serve_batches, "warmup": warm, "ms_per_step": head["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"served-{sw.resident.n_sets}", "resident_sets": sw.resident.n_sets,
+                   "batches": len(batches),
+                   "b_bits": args.bits if args.bits else "auto",
+                   "plain_service_rate": mu},
+        "latency": {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rho": 0.95},
+        "loads": loads,
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(line), flush=True)
 
 

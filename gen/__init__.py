@@ -192,3 +192,97 @@ def workload(name: str, n_sets: int | None = None, seed: int | None = None) -> C
     if seed is not None:
         g["seed"] = seed
     return generate(**g)
+
+
+# ---------------------------------------------------------------- batched form
+BATCH_THRESHOLDS = [(1, 2), (7, 10), (4, 5), (9, 10)]
+
+
+def batched_instances(n_instances: int = 256, seed: int = SEED_BASE + 3, n_min: int = 1_000,
+                      n_max: int = 200_000, size_hi: int = 2000):
+    """Many uneven self-join instances: ``[(Collection, (p, q)), ...]``.
+
+    Instance k: N_k = round(exp(U[ln n_min, ln n_max])) sets, log-normal sizes
+    with median m_k = exp(U[ln 5, ln 200]) and sigma 0.8 clipped to
+    2..size_hi, universe max(N_k, 50 m_k), Zipf exponent U[0.8, 1.3], 5% of
+    the sets in near-duplicate clusters, threshold drawn from 1/2, 7/10, 4/5,
+    9/10.  Instance parameters come from one seeded stream; each instance's
+    sets from its own seed."""
+    rng = np.random.Generator(np.random.PCG64(seed & 0xFFFFFFFFFFFFFFFF))
+    out = []
+    for k in range(n_instances):
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        m = float(np.exp(rng.uniform(np.log(5.0), np.log(200.0))))
+        s = float(rng.uniform(0.8, 1.3))
+        t = BATCH_THRESHOLDS[int(rng.integers(len(BATCH_THRESHOLDS)))]
+        u = max(n, int(round(50 * m)))
+        col = generate(n_sets=n, universe=u, zipf_s=s, size_dist=SIZE_LOGNORMAL, size_a=m,
+                       size_b=0.8, size_lo=2, size_hi=size_hi, planted_frac=0.05,
+                       seed=seed + ((k + 1) << 24))
+        out.append((col, t))
+    return out
+
+
+# ----------------------------------------------------------------- served form
+SERVE_THRESHOLDS = [(7, 10), (9, 10)]
+
+
+@dataclass
+class Served:
+    resident: Collection
+    batches: list          # [Collection]
+    thresholds: list       # [(p, q)] per batch
+    copies: list           # per batch: bool array, True where the set is a perturbed copy
+
+
+def _csr_slice(col: Collection, a: int, b: int) -> Collection:
+    off = col.offsets[a:b + 1]
+    return Collection(offsets=(off - off[0]).astype(np.uint64),
+                      tokens=col.tokens[int(off[0]):int(off[-1])].copy())
+
+
+def served_workload(n_batches: int, resident_sets: int = 5_000_000, seed: int = SEED_BASE + 4,
+                    max_batch: int = 10_000, copy_frac: float = 0.2, swap_frac: float = 0.1,
+                    universe: int = 2_000_000) -> Served:
+    """A resident collection and query batches against it.
+
+    One generated collection (Zipf 1.1, log-normal sizes median 30, sigma 0.8,
+    clipped 2..500) supplies both, so the token ids of resident and fresh sets
+    share one frequency order: the first ``resident_sets`` sets are resident,
+    the rest are fresh query sets.  Batch sizes are round(exp(U[0, ln
+    max_batch])); each query set is, with probability ``copy_frac``, a copy of
+    a uniformly chosen resident set with round(swap_frac * n) tokens replaced
+    by token occurrences drawn uniformly from the whole collection (so they
+    follow the global token frequencies), else the next fresh set.  The
+    threshold of each batch is 7/10 or 9/10."""
+    rng = np.random.Generator(np.random.PCG64((seed + 0x5E) & 0xFFFFFFFFFFFFFFFF))
+    sizes = np.round(np.exp(rng.uniform(0.0, np.log(max_batch), n_batches))).astype(np.int64)
+    is_copy = [rng.random(int(n)) < copy_frac for n in sizes]
+    n_fresh = int(sum(int((~c).sum()) for c in is_copy))
+    scale = (resident_sets + n_fresh) / 5_000_000
+    col = generate(n_sets=resident_sets + n_fresh, universe=max(64, int(round(universe * scale))),
+                   zipf_s=1.1, size_dist=SIZE_LOGNORMAL, size_a=30.0, size_b=0.8, size_lo=2,
+                   size_hi=500, seed=seed)
+    resident = _csr_slice(col, 0, resident_sets)
+    fresh_at = resident_sets
+    batches, thresholds = [], []
+    for b in range(n_batches):
+        sets = []
+        for cp in is_copy[b]:
+            if cp:
+                k = int(rng.integers(resident_sets))
+                base = resident.set(k)
+                n = base.shape[0]
+                n_swap = int(round(swap_frac * n))
+                keep = np.sort(rng.choice(n, size=n - n_swap, replace=False)) if n_swap else \
+                    np.arange(n)
+                cur = set(int(x) for x in base[keep])
+                while len(cur) < n:
+                    cur.add(int(col.tokens[int(rng.integers(col.n_tokens))]))
+                sets.append(np.array(sorted(cur), dtype=np.uint32))
+            else:
+                sets.append(col.set(fresh_at))
+                fresh_at += 1
+        batches.append(from_lists(sets))
+        thresholds.append(SERVE_THRESHOLDS[int(rng.integers(len(SERVE_THRESHOLDS)))])
+    return Served(resident=resident, batches=batches, thresholds=thresholds, copies=is_copy)

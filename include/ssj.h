@@ -33,7 +33,8 @@
  *     (ssj_pairs.pairs), released with ssj_free_pairs.  On any error
  *     *out is {NULL, 0}: there is never a partial result.
  *   - Calls are re-entrant; calls on distinct streams are independent.
- *     The library allocates its working memory per call.
+ *     The library takes its working memory per call from a per-device
+ *     cache of device memory chunks that it keeps until the process ends.
  *   - Return values are ssj_status codes; 0 is success.
  */
 #ifndef SSJ_H
@@ -53,11 +54,18 @@ typedef enum {
   SSJ_E_UNSORTED = -2,    /* a set is not strictly increasing */
   SSJ_E_NOMEM = -3,       /* a device or host allocation failed */
   SSJ_E_DEVICE = -4,      /* a HIP runtime call or kernel launch failed */
-  SSJ_E_UNSUPPORTED = -5  /* similarity function or generator not available */
+  SSJ_E_UNSUPPORTED = -5  /* sizes or widths beyond what the library handles */
 } ssj_status;
 
-/* Similarity functions of Table 1.  Jaccard |r n s| / |r u s| is the one
- * the paper's GPU algorithm (Alg. 8) evaluates. */
+/* Similarity functions of Table 1, with t = p / q:
+ *   Jaccard  |r n s| / |r u s|          >= t   (the one the paper's GPU
+ *                                               algorithm, Alg. 8, evaluates)
+ *   Dice     2 |r n s| / (|r| + |s|)    >= t
+ *   Cosine   |r n s| / sqrt(|r| |s|)    >= t
+ *   Overlap  |r n s|                    >= t   (t may exceed 1)
+ * Each is turned into the least overlap omin(|r|, |s|) that reaches t; the
+ * bitmap filter keeps a pair when its bound (Eq. 2) reaches omin, and the
+ * length filter is the function's row of Table 2. */
 typedef enum {
   SSJ_SIM_JACCARD = 0,
   SSJ_SIM_DICE = 1,
@@ -156,9 +164,9 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
  *                automatic width per class of row sizes (64, 128, 256 or
  *                512 bits, wider for larger sets, chosen from the expected
  *                bound of Section 3.4; bitmaps_dev must then be NULL)
- *   sim          ssj_sim; only SSJ_SIM_JACCARD is available (others
- *                return SSJ_E_UNSUPPORTED)
- *   p, q         threshold t = p / q, 1 <= p <= q (reduced internally)
+ *   sim          ssj_sim
+ *   p, q         threshold t = p / q, 1 <= p <= q (reduced internally);
+ *                SSJ_SIM_OVERLAP takes any p >= 1, q >= 1
  *   opts         NULL or knobs
  *   out          receives the pairs, ascending by (i, j), no duplicates
  *   stats        NULL or statistics
@@ -180,6 +188,80 @@ int ssj_self_join(const ssj_sets *s, const uint64_t *bitmaps_dev, uint32_t b_bit
 int ssj_rs_join(const ssj_sets *r, const uint64_t *r_bitmaps_dev, const ssj_sets *s,
                 const uint64_t *s_bitmaps_dev, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
                 const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream);
+
+/*
+ * ssj_self_join_batch -- many independent self-joins in one call (the
+ * batched form of Eq. 1 with R = S): instance k is the self-join of
+ * sets[k] at threshold p[k] / q[k].  All instances share the preparation,
+ * filter, verification and emission launches: the filter's tiles of every
+ * instance are handed out from the same work queue, so uneven instances
+ * keep the whole GPU busy.  With b_bits = 0 each instance gets its own
+ * widths per class of row sizes (the rule of ssj_self_join).
+ *   sets         n_instances collections (device CSR each, validated as
+ *                above); host array
+ *   n_instances  number of instances; 0 returns an empty result
+ *   p, q         host arrays of n_instances thresholds, 1 <= p[k] <= q[k]
+ *   b_bits       0 or a fixed width for every instance (as ssj_self_join;
+ *                no caller bitmaps)
+ *   sim          ssj_sim (every instance)
+ *   opts         NULL or knobs (shared by the instances)
+ *   out          every instance's pairs, instance by instance; each
+ *                instance's pairs are its caller indices (i < j), ascending
+ *                by (i, j) -- exactly what ssj_self_join returns for it
+ *   starts       NULL or a host array of n_instances + 1 entries: instance
+ *                k's pairs are out->pairs[starts[k] .. starts[k+1])
+ *   stats        NULL or totals over the instances
+ * Limits: the instances' total set count is below 2^32 - 1, and the bits
+ * of (instance, i, j) fit 64.  Errors as ssj_self_join; one bad instance
+ * fails the call.
+ */
+int ssj_self_join_batch(const ssj_sets *sets, uint32_t n_instances, const uint32_t *p,
+                        const uint32_t *q, uint32_t b_bits, int sim, const ssj_options *opts,
+                        ssj_pairs *out, uint64_t *starts, ssj_stats *stats, void *hip_stream);
+
+/* A resident collection S for repeated R-S queries (the served form). */
+typedef struct ssj_index ssj_index;
+
+/*
+ * ssj_index_create -- copy S into the index's own device memory, validate
+ * and size-sort it, and build its bitmaps once: Bitmap-Xor at every width
+ * the automatic mode may pick (64, 128, 256 and 512 bits) when b_bits is
+ * 0, else at b_bits.  The caller may free S afterwards.  The index lives on
+ * the current device until ssj_index_destroy.
+ *   s            the resident collection (device CSR)
+ *   b_bits       0 (automatic) or a fixed width, as ssj_self_join
+ *   out          receives the index; NULL on error
+ *   hip_stream   stream for the work; returns after it is synchronised
+ * Errors: SSJ_E_INVALID, SSJ_E_UNSORTED, SSJ_E_UNSUPPORTED, SSJ_E_NOMEM,
+ *         SSJ_E_DEVICE.
+ */
+int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *hip_stream);
+
+/*
+ * ssj_index_query -- R-S joins of query batches against the index (Eq. 1,
+ * R-S join): batch k's result is every pair (i in batches[k], j in S) with
+ * sim >= p[k] / q[k], exactly what ssj_rs_join(batches[k], S) returns.
+ * All batches of a call share the launches, as in ssj_self_join_batch.
+ * The index is only read: queries may run concurrently on distinct
+ * streams of the index's device.
+ *   idx          index from ssj_index_create (same current device)
+ *   batches      n_batches query collections (device CSR); host array
+ *   p, q         host arrays of n_batches thresholds
+ *   sim, opts    as ssj_rs_join
+ *   out          every batch's pairs, batch by batch, each ascending by
+ *                (i, j), i a caller index in the batch, j in S
+ *   starts       NULL or n_batches + 1 host entries, as ssj_self_join_batch
+ *   stats        NULL or totals over the batches
+ * Errors as ssj_rs_join; SSJ_E_INVALID also for a NULL index or another
+ * current device.
+ */
+int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
+                    const uint32_t *p, const uint32_t *q, int sim, const ssj_options *opts,
+                    ssj_pairs *out, uint64_t *starts, ssj_stats *stats, void *hip_stream);
+
+/* Release an index and its device memory (NULL-safe).  No query on it may
+ * still be running. */
+void ssj_index_destroy(ssj_index *idx);
 
 /* Release the pairs of a join.  NULL-safe and idempotent; zeroes *out. */
 void ssj_free_pairs(ssj_pairs *out);

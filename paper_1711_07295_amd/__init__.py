@@ -24,7 +24,8 @@ SSJ_SIM_JACCARD, SSJ_SIM_DICE, SSJ_SIM_COSINE, SSJ_SIM_OVERLAP = 0, 1, 2, 3
 SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT = 0, 1, 2
 SSJ_FLAG_SURVIVORS_ONLY = 1
 
-EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_free_pairs",
+EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
+           "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_free_pairs",
            "ssj_status_string", "ssj_abi_version")
 
 
@@ -93,6 +94,19 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ssj_options), ctypes.POINTER(ssj_pairs),
                                     ctypes.POINTER(ssj_stats), vp]
         lib.ssj_rs_join.restype = c_int
+        u32p, u64p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
+        lib.ssj_self_join_batch.argtypes = [sp, u32, u32p, u32p, u32, c_int,
+                                            ctypes.POINTER(ssj_options), ctypes.POINTER(ssj_pairs),
+                                            u64p, ctypes.POINTER(ssj_stats), vp]
+        lib.ssj_self_join_batch.restype = c_int
+        lib.ssj_index_create.argtypes = [sp, u32, ctypes.POINTER(vp), vp]
+        lib.ssj_index_create.restype = c_int
+        lib.ssj_index_query.argtypes = [vp, sp, u32, u32p, u32p, c_int,
+                                        ctypes.POINTER(ssj_options), ctypes.POINTER(ssj_pairs),
+                                        u64p, ctypes.POINTER(ssj_stats), vp]
+        lib.ssj_index_query.restype = c_int
+        lib.ssj_index_destroy.argtypes = [vp]
+        lib.ssj_index_destroy.restype = None
         lib.ssj_free_pairs.argtypes = [ctypes.POINTER(ssj_pairs)]
         lib.ssj_free_pairs.restype = None
         lib.ssj_status_string.argtypes = [c_int]
@@ -214,6 +228,86 @@ def ssj_rs_join(r: DeviceSets, s: DeviceSets, p: int, q: int, b_bits: int = 64, 
     if st != SSJ_OK:
         raise SsjError(st, "ssj_rs_join")
     return _take(out), stats.as_dict()
+
+
+def _tasks(cols, p, q):
+    n = len(cols)
+    if len(p) != n or len(q) != n:
+        raise ValueError("one threshold (p, q) per instance")
+    arr = (ssj_sets * max(n, 1))(*[c.c() for c in cols])
+    pa = (ctypes.c_uint32 * max(n, 1))(*[int(v) for v in p])
+    qa = (ctypes.c_uint32 * max(n, 1))(*[int(v) for v in q])
+    starts = (ctypes.c_uint64 * (n + 1))()
+    return n, arr, pa, qa, starts
+
+
+def _split(pairs: np.ndarray, starts, n: int):
+    st = np.ctypeslib.as_array(starts, shape=(n + 1,)).astype(np.int64)
+    return [pairs[st[k]:st[k + 1]] for k in range(n)]
+
+
+def ssj_self_join_batch(instances, p, q, b_bits: int = 0, sim: int = SSJ_SIM_JACCARD,
+                        queue_capacity: int = 0, tile_cols: int = 0, flags: int = 0,
+                        stream=None):
+    """Self-join of every instance (DeviceSets) at its own threshold p[k]/q[k],
+    all in one call.  Returns ([pairs of instance k], totals stats dict)."""
+    n, arr, pa, qa, starts = _tasks(instances, p, q)
+    out, stats = ssj_pairs(), ssj_stats()
+    o = _opts(queue_capacity, tile_cols, flags)
+    st = load().ssj_self_join_batch(arr, n, pa, qa, b_bits, sim, ctypes.byref(o) if o else None,
+                                    ctypes.byref(out), starts, ctypes.byref(stats),
+                                    _stream(stream))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_self_join_batch")
+    return _split(_take(out), starts, n), stats.as_dict()
+
+
+class Index:
+    """A resident collection S for repeated R-S queries (ssj_index_*)."""
+
+    def __init__(self, sets: DeviceSets, b_bits: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        cs = sets.c()
+        st = load().ssj_index_create(ctypes.byref(cs), b_bits, ctypes.byref(self._h),
+                                     _stream(stream))
+        if st != SSJ_OK:
+            self._h = ctypes.c_void_p()
+            raise SsjError(st, "ssj_index_create")
+        self.n_sets = sets.n_sets
+        self.b_bits = b_bits
+
+    def query(self, batches, p, q, sim: int = SSJ_SIM_JACCARD, queue_capacity: int = 0,
+              tile_cols: int = 0, flags: int = 0, stream=None):
+        """R-S join of every batch (DeviceSets) against S at p[k]/q[k], in one
+        call.  Returns ([pairs of batch k], totals stats dict)."""
+        if not self._h:
+            raise RuntimeError("index is closed")
+        n, arr, pa, qa, starts = _tasks(batches, p, q)
+        out, stats = ssj_pairs(), ssj_stats()
+        o = _opts(queue_capacity, tile_cols, flags)
+        st = load().ssj_index_query(self._h, arr, n, pa, qa, sim, ctypes.byref(o) if o else None,
+                                    ctypes.byref(out), starts, ctypes.byref(stats),
+                                    _stream(stream))
+        if st != SSJ_OK:
+            raise SsjError(st, "ssj_index_query")
+        return _split(_take(out), starts, n), stats.as_dict()
+
+    def close(self):
+        if self._h:
+            load().ssj_index_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ssj_free_pairs(out: ssj_pairs) -> None:

@@ -9,6 +9,9 @@
 //     bit h(t) or the next free bit after it, cyclically.  The occupied
 //     bits do not depend on the order the tokens are taken in.
 //
+// The sets come from one or more sides (collections) laid out one after the
+// other in a space of global indices (see SideDesc).
+//
 // One wave per set: lanes stride over the set's tokens (coalesced reads of
 // the CSR token array), combine their bits in a per-wave LDS bitmap with
 // LDS atomics, and lane w writes word w.  The kernel is bound by HBM reads
@@ -20,10 +23,25 @@ namespace {
 
 constexpr int kWavesPerBlock = kBlock / 64;
 
+// Side of workgroup blk of the segmented build: the last side whose first
+// workgroup is <= blk (empty sides share it with the next side).
+__device__ __forceinline__ uint32_t side_of_block(const SideDesc *__restrict__ sides,
+                                                  uint32_t n_sides, uint32_t blk) {
+  uint32_t lo = 0, hi = n_sides;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sides[mid].blk0 <= blk) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One wave per output row x: in size order (perm/side_of given) the set
+// perm[x] of side side_of[x], otherwise the caller set x - base of the side
+// holding global index x.
 template <int METHOD, bool POW2>
 __global__ __launch_bounds__(kBlock) void k_build_bitmaps(
-    const uint64_t *__restrict__ offsets, const uint32_t *__restrict__ tokens,
-    const uint32_t *__restrict__ perm, uint64_t n, uint32_t b_bits, uint32_t out_words,
+    const SideDesc *__restrict__ sides, uint32_t n_sides, const uint32_t *__restrict__ perm,
+    const uint32_t *__restrict__ side_of, uint64_t n, uint32_t b_bits, uint32_t out_words,
     uint64_t *__restrict__ out, JoinCounters *__restrict__ ctr) {
   __shared__ uint32_t lbits[kWavesPerBlock][2 * kMaxWords];
   const int lane = threadIdx.x & 63;
@@ -32,9 +50,12 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps(
   if (x >= n) return;  // whole wave leaves together
   uint32_t *bits = lbits[w];
   for (uint32_t i = lane; i < 2 * out_words; i += 64) bits[i] = 0;
-  const uint64_t k = perm ? perm[x] : x;
-  if (k >= n) return;
-  const uint64_t o0 = offsets[k], o1 = offsets[k + 1];
+  const uint32_t sid = perm ? side_of[x] : side_of_index(sides, n_sides, x);
+  const SideDesc sd = sides[sid];
+  const uint64_t k = perm ? perm[x] : x - sd.base;
+  if (k >= sd.n) return;
+  const uint32_t *__restrict__ tokens = sd.tokens;
+  const uint64_t o0 = sd.offsets[k], o1 = sd.offsets[k + 1];
   const uint32_t nt = (uint32_t)(o1 - o0);
   const uint32_t mask = b_bits - 1;
   bool unsorted = false;
@@ -80,13 +101,16 @@ constexpr uint32_t kSegSets = 256;
 
 template <int WO, int METHOD, bool POW2>
 __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
-    const uint64_t *__restrict__ offsets, const uint32_t *__restrict__ tokens,
-    const uint32_t *__restrict__ rank, uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out,
-    JoinCounters *__restrict__ ctr) {
+    const SideDesc *__restrict__ sides, uint32_t n_sides, const uint32_t *__restrict__ rank,
+    uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out, JoinCounters *__restrict__ ctr) {
   __shared__ uint64_t soff[kSegSets + 1];
   __shared__ uint32_t sbits[kSegSets * 2 * WO];
-  const uint64_t s0 = (uint64_t)blockIdx.x * kSegSets;
-  const uint32_t ns = (uint32_t)min((uint64_t)kSegSets, n - s0);
+  const SideDesc sd = sides[side_of_block(sides, n_sides, blockIdx.x)];
+  const uint64_t s0 = (uint64_t)(blockIdx.x - sd.blk0) * kSegSets;
+  if (s0 >= sd.n) return;  // whole workgroup leaves together
+  const uint32_t ns = (uint32_t)min((uint64_t)kSegSets, sd.n - s0);
+  const uint64_t *__restrict__ offsets = sd.offsets;
+  const uint32_t *__restrict__ tokens = sd.tokens;
   const uint64_t t0 = offsets[s0];
   for (uint32_t i = threadIdx.x; i <= ns; i += kBlock) soff[i] = offsets[s0 + i] - t0;
   for (uint32_t i = threadIdx.x; i < ns * 2 * WO; i += kBlock) sbits[i] = 0;
@@ -109,21 +133,12 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < ns * WO; i += kBlock) {
     const uint32_t x = i / WO, w = i - x * WO;
-    const uint64_t row = rank ? rank[s0 + x] : s0 + x;
+    const uint64_t row = rank ? rank[sd.base + s0 + x] : sd.base + s0 + x;
     if (row < n)
       out[row * WO + w] = (uint64_t)sbits[x * 2 * WO + 2 * w] |
                           ((uint64_t)sbits[x * 2 * WO + 2 * w + 1] << 32);
   }
   if (__ballot(unsorted) && (threadIdx.x & 63) == 0) atomicOr(&ctr->error, kErrUnsorted);
-}
-
-__global__ __launch_bounds__(kBlock) void k_invert_perm(const uint32_t *__restrict__ perm,
-                                                        uint64_t n, uint32_t *__restrict__ rank) {
-  const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (x < n) {
-    const uint32_t k = perm[x];
-    if (k < n) rank[k] = (uint32_t)x;
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_sorted(const uint64_t *__restrict__ offsets,
@@ -152,67 +167,67 @@ __global__ __launch_bounds__(kBlock) void k_gather_bitmaps(const uint64_t *__res
 }
 
 template <int WO, int METHOD>
-hipError_t launch_seg(bool pow2, hipStream_t st, const uint64_t *offsets,
-                      const uint32_t *tokens, const uint32_t *rank, uint64_t n, uint32_t b_bits,
+hipError_t launch_seg(bool pow2, hipStream_t st, const SideDesc *sides, uint32_t n_sides,
+                      uint32_t seg_blocks, const uint32_t *rank, uint64_t n, uint32_t b_bits,
                       uint64_t *out, JoinCounters *ctr) {
-  dim3 grid((unsigned)((n + kSegSets - 1) / kSegSets));
+  dim3 grid(seg_blocks);
   if (pow2)
     hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, true>), grid, dim3(kBlock), 0, st,
-                       offsets, tokens, rank, n, b_bits, out, ctr);
+                       sides, n_sides, rank, n, b_bits, out, ctr);
   else
     hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, false>), grid, dim3(kBlock), 0, st,
-                       offsets, tokens, rank, n, b_bits, out, ctr);
+                       sides, n_sides, rank, n, b_bits, out, ctr);
   return hipGetLastError();
 }
 
 template <int METHOD>
-hipError_t launch_method(bool pow2, dim3 grid, hipStream_t st, const uint64_t *offsets,
-                         const uint32_t *tokens, const uint32_t *perm, const uint32_t *rank,
-                         uint64_t n, uint32_t b_bits, uint32_t out_words, uint64_t *out,
-                         JoinCounters *ctr) {
-  if (METHOD != SSJ_BM_NEXT && (rank || !perm)) {
+hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint32_t n_sides,
+                         uint32_t seg_blocks, uint64_t n, const uint32_t *perm,
+                         const uint32_t *rank, const uint32_t *side_of, uint32_t b_bits,
+                         uint32_t out_words, uint64_t *out, JoinCounters *ctr) {
+  if (METHOD != SSJ_BM_NEXT && (rank || !perm) && seg_blocks) {
+#define SSJ_SEG(wo) \
+  case wo:          \
+    return launch_seg<wo, METHOD>(pow2, st, sides, n_sides, seg_blocks, rank, n, b_bits, out, ctr);
     switch (out_words) {
-      case 1: return launch_seg<1, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 2: return launch_seg<2, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 3: return launch_seg<3, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 4: return launch_seg<4, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 5: return launch_seg<5, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 6: return launch_seg<6, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 7: return launch_seg<7, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
-      case 8: return launch_seg<8, METHOD>(pow2, st, offsets, tokens, rank, n, b_bits, out, ctr);
+      SSJ_SEG(1) SSJ_SEG(2) SSJ_SEG(3) SSJ_SEG(4) SSJ_SEG(5) SSJ_SEG(6) SSJ_SEG(7) SSJ_SEG(8)
       default: break;
     }
+#undef SSJ_SEG
   }
+  dim3 grid((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock));
   if (pow2)
-    hipLaunchKernelGGL((k_build_bitmaps<METHOD, true>), grid, dim3(kBlock), 0, st, offsets,
-                       tokens, perm, n, b_bits, out_words, out, ctr);
+    hipLaunchKernelGGL((k_build_bitmaps<METHOD, true>), grid, dim3(kBlock), 0, st, sides,
+                       n_sides, perm, side_of, n, b_bits, out_words, out, ctr);
   else
-    hipLaunchKernelGGL((k_build_bitmaps<METHOD, false>), grid, dim3(kBlock), 0, st, offsets,
-                       tokens, perm, n, b_bits, out_words, out, ctr);
+    hipLaunchKernelGGL((k_build_bitmaps<METHOD, false>), grid, dim3(kBlock), 0, st, sides,
+                       n_sides, perm, side_of, n, b_bits, out_words, out, ctr);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
-                                const uint32_t *perm, const uint32_t *rank, uint64_t n,
-                                uint32_t b_bits, int method,
+uint32_t bitmap_seg_blocks(uint64_t n) { return (uint32_t)((n + kSegSets - 1) / kSegSets); }
+
+hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_t seg_blocks,
+                                uint64_t n_total, const uint32_t *perm, const uint32_t *rank,
+                                const uint32_t *side_of, uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
                                 hipStream_t st) {
-  if (n == 0) return hipSuccess;
+  if (n_total == 0) return hipSuccess;
   if (out_words > kMaxWords || out_words < b_bits / 64) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock));
-  bool pow2 = (b_bits & (b_bits - 1)) == 0;
+  if (perm && !side_of) return hipErrorInvalidValue;
+  const bool pow2 = (b_bits & (b_bits - 1)) == 0;
   switch (method) {
     case SSJ_BM_XOR:
-      return launch_method<SSJ_BM_XOR>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
-                                       out_words, out, ctr);
+      return launch_method<SSJ_BM_XOR>(pow2, st, sides, n_sides, seg_blocks, n_total, perm, rank,
+                                       side_of, b_bits, out_words, out, ctr);
     case SSJ_BM_SET:
-      return launch_method<SSJ_BM_SET>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
-                                       out_words, out, ctr);
+      return launch_method<SSJ_BM_SET>(pow2, st, sides, n_sides, seg_blocks, n_total, perm, rank,
+                                       side_of, b_bits, out_words, out, ctr);
     case SSJ_BM_NEXT:
-      return launch_method<SSJ_BM_NEXT>(pow2, grid, st, offsets, tokens, perm, rank, n, b_bits,
-                                        out_words, out, ctr);
+      return launch_method<SSJ_BM_NEXT>(pow2, st, sides, n_sides, seg_blocks, n_total, perm,
+                                        rank, side_of, b_bits, out_words, out, ctr);
     default:
       return hipErrorInvalidValue;
   }
@@ -237,13 +252,4 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
   return hipGetLastError();
 }
 
-}  // namespace ssj
-
-namespace ssj {
-hipError_t launch_invert_perm(const uint32_t *perm, uint64_t n, uint32_t *rank, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_invert_perm, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     st, perm, n, rank);
-  return hipGetLastError();
-}
 }  // namespace ssj

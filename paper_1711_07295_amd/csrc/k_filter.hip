@@ -198,12 +198,13 @@ __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_rows,
 // One tile: rows [row0, row_end) of a row block (at most 64*R of them, R per
 // lane, interleaved by 64), columns [c0, c1).  Returns false when the queue
 // filled (a resume point has been recorded).
-template <int W, int R, int U>
+template <int W, int R, int U, bool COS>
 __device__ __forceinline__ bool run_tile(
     const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
     const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
-    const uint32_t *__restrict__ sstart_cols, const int32_t *__restrict__ slack,
-    const uint32_t *__restrict__ cmin, const uint32_t *__restrict__ cmax, uint32_t row0,
+    const uint32_t *__restrict__ sstart_cols, uint32_t col_base,
+    const int32_t *__restrict__ slack, const uint32_t *__restrict__ cmin,
+    const uint32_t *__restrict__ cmax, bool cosine, uint32_t p, uint32_t q, uint32_t row0,
     uint32_t row_end, uint32_t c0, uint32_t c1, bool diag, uint32_t first_slab, Sink &sink) {
   const uint32_t lane = threadIdx.x & 63;
   Rows<W, R> rw;
@@ -230,13 +231,15 @@ __device__ __forceinline__ bool run_tile(
   uint32_t j = c0;
   while (j < c1) {
     const uint32_t c = rfl(size_cols[j]);
-    const uint32_t g1 = min(max(rfl(sstart_cols[c + 1]), j + 1), c1);  // always advances
+    const uint32_t g1 = min(max(col_base + rfl(sstart_cols[c + 1]), j + 1), c1);  // advances
     int32_t thr[R];
     bool any_ok = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool in_band = c >= rw.cmn[r] && c <= rw.cmx[r];
-      thr[r] = in_band ? slack[rw.size[r] + c] : -1;
+      if (!in_band) thr[r] = -1;
+      else if (COS && cosine) thr[r] = cosine_slack(rw.size[r], c, p, q);
+      else thr[r] = slack[rw.size[r] + c];
       any_ok |= in_band;
     }
     // resumed inside column j: its slabs below first_slab are already queued,
@@ -262,13 +265,13 @@ __device__ __forceinline__ bool run_tile(
 // Waves first take the resume entries of a previous launch that fall in
 // that range (entry k goes to wave k), then tiles from the partitioned
 // cursors, until the range is exhausted or the queue has filled.
-template <int W, int R, int U>
+template <int W, int R, int U, bool COS>
 __global__ __launch_bounds__(kBlock) void k_filter(
     const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
     const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
-    const uint32_t *__restrict__ sstart_cols, const int32_t *__restrict__ slack,
-    const uint32_t *__restrict__ cmin, const uint32_t *__restrict__ cmax,
-    const RowBlock *__restrict__ blocks, const uint32_t *__restrict__ tile_block,
+    const uint32_t *__restrict__ sstart_cols, const uint32_t *__restrict__ tables,
+    const TaskDesc *__restrict__ tasks, const RowBlock *__restrict__ blocks,
+    const uint32_t *__restrict__ tile_block,
     uint2 *__restrict__ queue, JoinCounters *__restrict__ ctr,
     const Resume *__restrict__ resume_in, Resume *__restrict__ resume_out, FilterConfig cfg) {
   const uint32_t lane = threadIdx.x & 63;
@@ -325,9 +328,19 @@ __global__ __launch_bounds__(kBlock) void k_filter(
     const uint32_t cbeg = rfl(blocks[b].col_begin);
     const uint32_t cend = rfl(blocks[b].col_end);
     const uint32_t k = t - rfl(blocks[b].tile_begin);
+    const uint32_t task = rfl(blocks[b].task);
+    const bool self = rfl(blocks[b].self) != 0;
+    const TaskDesc *td = tasks + task;
+    const int32_t *slack = reinterpret_cast<const int32_t *>(tables + rfl(td->slack_off));
+    const uint32_t *cmin = tables + rfl(td->cmin_off);
+    const uint32_t *cmax = tables + rfl(td->cmax_off);
+    const uint32_t *sstart = sstart_cols + rfl64(td->col_sstart_off);
+    const uint32_t col_base = rfl(td->col_base);
+    const bool cosine = rfl(td->sim) == SSJ_SIM_COSINE;
+    const uint32_t tp = rfl(td->p), tq = rfl(td->q);
     uint32_t c0, c1;
     bool diag = false;
-    if (cfg.self) {
+    if (self) {
       const uint32_t n_int = (row0 - cbeg + cfg.tile_cols - 1) / cfg.tile_cols;
       if (k < n_int) {
         c0 = cbeg + k * cfg.tile_cols;
@@ -347,9 +360,9 @@ __global__ __launch_bounds__(kBlock) void k_filter(
       first_slab = slab;
     }
     resumed = false;
-    if (!run_tile<W, R, U>(bm_rows, bm_cols, size_rows, size_cols, sstart_cols, slack, cmin,
-                           cmax, row0, min(row_end, cfg.n_rows), c0, c1, diag, first_slab,
-                           sink)) {
+    if (!run_tile<W, R, U, COS>(bm_rows, bm_cols, size_rows, size_cols, sstart, col_base, slack, cmin,
+                           cmax, cosine, tp, tq, row0, min(row_end, cfg.n_rows), c0,
+                           min(c1, cfg.n_cols), diag, first_slab, sink)) {
       // the queue is full: record where this tile resumes, and stop
       const uint32_t fcol = rfl(sink.fail_col), fslab = rfl(sink.fail_slab);
       if (lane == 0) {
@@ -367,10 +380,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(
   }
 }
 
-template <int W, int R, int U>
+template <int W, int R, int U, bool COS>
 hipError_t launch_shape(dim3 grid, hipStream_t st, const FilterArgs &a) {
-  hipLaunchKernelGGL((k_filter<W, R, U>), grid, dim3(kBlock), 0, st, a.bm_rows, a.bm_cols,
-                     a.size_rows, a.size_cols, a.sstart_cols, a.slack, a.cmin, a.cmax, a.blocks,
+  hipLaunchKernelGGL((k_filter<W, R, U, COS>), grid, dim3(kBlock), 0, st, a.bm_rows, a.bm_cols,
+                     a.size_rows, a.size_cols, a.sstart_cols, a.tables, a.tasks, a.blocks,
                      a.tile_block, a.queue, a.ctr, a.resume_in, a.resume_out, a.cfg);
   return hipGetLastError();
 }
@@ -427,10 +440,13 @@ int filter_grid_blocks() {
   return cus * 8;  // 32 waves per CU
 }
 
-hipError_t launch_filter(uint32_t padded_words, const FilterArgs &a, hipStream_t st) {
+hipError_t launch_filter(uint32_t padded_words, bool cosine, const FilterArgs &a,
+                         hipStream_t st) {
   dim3 grid(filter_grid_blocks());
-#define X(w, r, u) \
-  if (padded_words == (w)) return launch_shape<w, r, u>(grid, st, a);
+#define X(w, r, u)                                              \
+  if (padded_words == (w))                                      \
+    return cosine ? launch_shape<w, r, u, true>(grid, st, a)    \
+                  : launch_shape<w, r, u, false>(grid, st, a);
   SSJ_FILTER_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

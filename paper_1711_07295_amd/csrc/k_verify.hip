@@ -1,13 +1,15 @@
 // Exact verification of the bitmap filter's survivors (the verify step the
 // paper's GPU algorithm leaves to the host, Alg. 8, done here on the GPU).
 //
-// Each queue entry (i, j) names a row and a column in size order; the
-// sets are the caller's CSR sets perm_rows[i] and perm_cols[j].  The overlap
-// o = |r n s| comes from one sorted merge that stops as soon as even
-// matching every remaining token could not reach omin(|r| + |s|), the least
-// overlap that meets the threshold (Table 1, integer form).  A qualifying
-// pair is written as a 64-bit key of caller indices, (min, max) for the
-// self-join and (r, s) for the R-S join.
+// Each queue entry (i, j) names a row and a column (global size-order
+// indices of the row and column spaces); the sets are the caller's CSR sets
+// perm[i] of side side_of[i] and perm[j] of side side_of[j], and the task is
+// the one of the row's side.  The overlap o = |r n s| comes from one sorted
+// merge that stops as soon as even matching every remaining token could not
+// reach omin(|r| + |s|), the least overlap that meets the task's threshold
+// (Table 1, integer form).  A qualifying pair is written as a 64-bit key
+// (task, caller i, caller j), (min, max) for a self-join task and (r, s) for
+// an R-S task, so that one radix sort orders the results of every task.
 //
 // Grid-stride over the queue, one survivor per lane; results are appended
 // with one atomic per wave (ballot + lane rank).
@@ -66,12 +68,9 @@ __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restr
 }
 
 __global__ __launch_bounds__(kBlock) void k_verify(
-    const uint2 *__restrict__ queue, unsigned long long cap,
-    const uint64_t *__restrict__ off_rows, const uint32_t *__restrict__ tok_rows,
-    const uint32_t *__restrict__ perm_rows, const uint64_t *__restrict__ off_cols,
-    const uint32_t *__restrict__ tok_cols, const uint32_t *__restrict__ perm_cols,
-    const uint32_t *__restrict__ omin, uint32_t n_rows, uint32_t n_cols, uint32_t self,
-    uint32_t survivors_only,
+    const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
+    const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
+    const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only,
     unsigned long long *__restrict__ results, unsigned long long results_cap,
     JoinCounters *__restrict__ ctr) {
   const uint32_t lane = threadIdx.x & 63;
@@ -81,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
   const unsigned long long start = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
   // every lane of a wave runs the same number of iterations
   const unsigned long long wave0 = start - lane;
+  const int tshift = ib + jb;
   uint32_t surv = 0;
   for (unsigned long long e0 = wave0; e0 < count; e0 += stride) {
     const unsigned long long e = e0 + lane;
@@ -88,25 +88,31 @@ __global__ __launch_bounds__(kBlock) void k_verify(
     unsigned long long key = 0;
     if (e < count) {
       const uint2 qe = queue[e];
-      if (qe.x < n_rows && qe.y < n_cols) {
+      if (qe.x < rows.n && qe.y < cols.n) {
         ++surv;
-        const uint32_t x = perm_rows[qe.x], y = perm_cols[qe.y];
-        const uint64_t r0 = off_rows[x], r1 = off_rows[x + 1];
-        const uint64_t s0 = off_cols[y], s1 = off_cols[y + 1];
+        const SideDesc dr = rows.sides[rows.side_of[qe.x]];
+        const SideDesc dc = cols.sides[cols.side_of[qe.y]];
+        const uint32_t task = side_task[rows.side_of[qe.x]];
+        const uint32_t x = rows.perm[qe.x], y = cols.perm[qe.y];
+        const uint64_t r0 = dr.offsets[x], r1 = dr.offsets[x + 1];
+        const uint64_t s0 = dc.offsets[y], s1 = dc.offsets[y + 1];
         const uint32_t a = (uint32_t)(r1 - r0), c = (uint32_t)(s1 - s0);
         if (survivors_only) {
           hit = true;
         } else {
-          hit = a != 0 && c != 0 && overlap_reaches(tok_rows + r0, a, tok_cols + s0, c,
-                                                   omin[a + c]);
+          const TaskDesc &td = tasks[task];
+          const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
+                                                         : tables[td.omin_off + a + c];
+          hit = a != 0 && c != 0 && overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
         }
         if (hit) {
-          if (self) {
-            const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-            key = ((unsigned long long)lo << 32) | hi;
-          } else {
-            key = ((unsigned long long)x << 32) | y;
+          uint32_t ki = x, kj = y;
+          if (tasks[task].self && y < x) {
+            ki = y;
+            kj = x;
           }
+          key = ((unsigned long long)ki << jb) | kj;
+          if (tshift < 64) key |= (unsigned long long)task << tshift;
         }
       }
     }
@@ -127,20 +133,49 @@ __global__ __launch_bounds__(kBlock) void k_verify(
   if (lane == 0 && s) atomicAdd(&ctr->survivors, (unsigned long long)s);
 }
 
+// Sorted keys -> pairs, and the first result of every task: the key at x
+// opens tasks (task(x-1), task(x)]; the last key closes the rest.
+__global__ __launch_bounds__(kBlock) void k_split_results(
+    const unsigned long long *__restrict__ keys, uint64_t n, int ib, int jb, uint32_t n_tasks,
+    ssj_pair *__restrict__ out, uint64_t *__restrict__ task_start) {
+  const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (x >= n) return;
+  const int tshift = ib + jb;
+  auto task_of = [&](unsigned long long k) -> uint32_t {
+    return tshift < 64 ? (uint32_t)(k >> tshift) : 0u;
+  };
+  const unsigned long long k = keys[x];
+  const uint32_t t = task_of(k);
+  ssj_pair pr;
+  pr.i = (uint32_t)((k >> jb) & ((1ull << ib) - 1));
+  pr.j = (uint32_t)(k & ((1ull << jb) - 1));
+  out[x] = pr;
+  const uint32_t t_prev = x ? task_of(keys[x - 1]) : 0u;
+  for (uint32_t u = x ? t_prev + 1 : 0u; u <= t && u <= n_tasks; ++u) task_start[u] = x;
+  if (x + 1 == n)
+    for (uint32_t u = t + 1; u <= n_tasks; ++u) task_start[u] = n;
+}
+
 }  // namespace
 
-hipError_t launch_verify(const uint2 *queue, unsigned long long cap, const uint64_t *off_rows,
-                         const uint32_t *tok_rows, const uint32_t *perm_rows,
-                         const uint64_t *off_cols, const uint32_t *tok_cols,
-                         const uint32_t *perm_cols, const uint32_t *omin, uint32_t n_rows,
-                         uint32_t n_cols, uint32_t self,
-                         uint32_t survivors_only, unsigned long long *results,
-                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st) {
+hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
+                         VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
+                         const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
+                         unsigned long long *results, unsigned long long results_cap,
+                         JoinCounters *ctr, hipStream_t st) {
   dim3 grid(filter_grid_blocks());
-  hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, off_rows, tok_rows,
-                     perm_rows, off_cols, tok_cols, perm_cols, omin, n_rows, n_cols, self,
-                     survivors_only,
-                     results, results_cap, ctr);
+  hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
+                     tasks, tables, ib, jb, survivors_only, results, results_cap, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_results(const unsigned long long *keys, uint64_t n, int ib, int jb,
+                                uint32_t n_tasks, ssj_pair *out, uint64_t *task_start,
+                                hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (ib < 1 || jb < 1 || ib > 32 || jb > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split_results, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, st, keys, n, ib, jb, n_tasks, out, task_start);
   return hipGetLastError();
 }
 

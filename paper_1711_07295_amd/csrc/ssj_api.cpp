@@ -1,8 +1,15 @@
 // C-ABI host layer of the library: argument checks, the size-ordered
-// preparation of each collection, the tile plan of the length band, the
+// preparation of the collections, the tile plan of the length band, the
 // filter/verify rounds over a bounded survivor queue, and the emission of
-// the sorted result pairs.  Every step of the join runs in the library's
-// own kernels; the host only plans, launches and copies.
+// the sorted result pairs.  Every step of a join runs in the library's own
+// kernels; the host only plans, launches and copies.
+//
+// One call joins one or more tasks.  The sets of a call live in two spaces
+// (rows and columns), each a list of sides (collections) laid out one after
+// the other; a task joins one row side with one column side at its own
+// threshold.  A self-join is one task whose row and column side coincide;
+// a batch of self-joins is many such tasks in one space; a query against a
+// resident index is one task per query batch, all against the index's side.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,7 +18,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <vector>
 
@@ -80,24 +89,40 @@ class ChunkCache {
   std::vector<Chunk> free_[64];
 };
 
-// Device memory of one call, carved from cached chunks.  The destructor
-// returns the chunks; every exit path synchronises the stream first.
+// Bump allocator over device memory chunks.  A call's arena takes cached
+// chunks and returns them when it ends, after synchronising its stream; an
+// owned arena (a resident index) allocates its own and frees them when it is
+// destroyed (hipFree waits for the device).
 class Arena {
  public:
-  explicit Arena(hipStream_t st) : st_(st) {
+  explicit Arena(hipStream_t st, bool owned = false) : st_(st), owned_(owned) {
     if (hipGetDevice(&dev_) != hipSuccess) dev_ = 0;
   }
+  Arena(const Arena &) = delete;
+  Arena &operator=(const Arena &) = delete;
   ~Arena() {
-    (void)hipStreamSynchronize(st_);
-    for (auto &c : chunks_) ChunkCache::get().give(dev_, c.first, c.second);
+    if (!owned_) (void)hipStreamSynchronize(st_);
+    for (auto &c : chunks_) {
+      if (owned_) (void)hipFree(c.first);
+      else ChunkCache::get().give(dev_, c.first, c.second);
+    }
   }
   template <class T>
   T *alloc(uint64_t n) {
     uint64_t bytes = (std::max<uint64_t>(n, 1) * sizeof(T) + 255) & ~255ull;
     if (bytes > left_) {
-      uint64_t size = kChunk;
-      while (size < bytes) size <<= 1;
-      void *p = ChunkCache::get().take(dev_, size);
+      uint64_t size = owned_ ? std::max<uint64_t>(bytes, kOwnedChunk) : kChunk;
+      if (!owned_)
+        while (size < bytes) size <<= 1;
+      void *p = nullptr;
+      if (owned_) {
+        if (hipMalloc(&p, size) != hipSuccess) {
+          (void)hipGetLastError();
+          p = nullptr;
+        }
+      } else {
+        p = ChunkCache::get().take(dev_, size);
+      }
       if (!p) throw Fail{SSJ_E_NOMEM};
       chunks_.push_back({p, size});
       next_ = static_cast<char *>(p);
@@ -108,10 +133,13 @@ class Arena {
     left_ -= bytes;
     return out;
   }
+  int device() const { return dev_; }
 
  private:
   static constexpr uint64_t kChunk = 64ull << 20;
+  static constexpr uint64_t kOwnedChunk = 16ull << 20;
   hipStream_t st_;
+  bool owned_;
   int dev_ = 0;
   std::vector<std::pair<void *, uint64_t>> chunks_;
   char *next_ = nullptr;
@@ -139,102 +167,213 @@ int bits_for(uint64_t v) {
   return b;
 }
 
-// One collection, validated and in size order.
-struct Side {
-  const ssj_sets *in = nullptr;
-  uint64_t n = 0;
-  uint32_t max_size = 0;
-  uint32_t *sizes = nullptr;   // size order
-  uint32_t *perm = nullptr;    // size order -> caller index
-  uint32_t *rank = nullptr;    // caller index -> size order
-  uint32_t *sstart = nullptr;  // [max_size + 2]
-  std::vector<uint32_t> sstart_h;
-  uint64_t *bm = nullptr;      // size-order bitmaps of every width, one after the other
-  uint32_t first_nonempty() const { return sstart_h.size() > 1 ? sstart_h[1] : (uint32_t)n; }
-  uint64_t count_of(uint32_t s) const { return (uint64_t)sstart_h[s + 1] - sstart_h[s]; }
-};
-
 void validate_sets(const ssj_sets *s) {
   if (!s) throw Fail{SSJ_E_INVALID};
   if (s->n_sets >= 0xFFFFFFFFull) throw Fail{SSJ_E_INVALID};
   if (s->n_sets > 0 && !s->offsets) throw Fail{SSJ_E_INVALID};
   if (s->n_tokens > 0 && !s->tokens) throw Fail{SSJ_E_INVALID};
+  if (s->n_sets == 0 && s->n_tokens != 0) throw Fail{SSJ_E_INVALID};
 }
 
-// Sizes and offset check (one sync for the largest size), stable size sort,
-// group starts (copied to the host; the caller synchronises).
-void order(Side &sd, const ssj_sets *s, Arena &ar, hipStream_t st) {
-  sd.in = s;
-  sd.n = s->n_sets;
-  const uint64_t n = sd.n;
-  JoinCounters *ctr = ar.alloc<JoinCounters>(1);
-  JoinCounters ctr_h;
-  check(launch_reset_all(ctr, st));
-  unsigned long long *keys = ar.alloc<unsigned long long>(n);
-  check(launch_set_sizes(s->offsets, n, s->n_tokens, keys, ctr, st));
-  d2h(&ctr_h, ctr, 1, st);
-  sync(st);
-  if (ctr_h.error & (kErrOffsets | kErrTooBig)) throw Fail{SSJ_E_INVALID};
-  if (n == 0 && s->n_tokens != 0) throw Fail{SSJ_E_INVALID};
-  sd.max_size = ctr_h.max_size;
-  if ((uint64_t)sd.max_size * 2 + 2 > kMaxTable) throw Fail{SSJ_E_UNSUPPORTED};
+// ------------------------------------------------------------------ spaces
 
-  // stable sort by size: keys (size << 32 | index), digits of the size only
-  unsigned long long *tmp = ar.alloc<unsigned long long>(n);
-  uint32_t *scr = ar.alloc<uint32_t>(radix_scratch_words(n));
-  int shifts[4], ns = 0;
-  for (int b = 0; b < bits_for(sd.max_size); b += 8) shifts[ns++] = 32 + b;
-  unsigned long long *sorted = keys;
-  check(radix_sort_u64(keys, tmp, n, shifts, ns, scr, st, &sorted));
-  sd.sizes = ar.alloc<uint32_t>(n);
-  sd.perm = ar.alloc<uint32_t>(n);
-  check(launch_unpack_keys(sorted, n, sd.sizes, sd.perm, st));
-  sd.sstart = ar.alloc<uint32_t>((uint64_t)sd.max_size + 2);
-  check(launch_group_starts(sd.sizes, n, sd.max_size, sd.sstart, st));
-  sd.sstart_h.assign((size_t)sd.max_size + 2, 0);
-  d2h(sd.sstart_h.data(), sd.sstart, sd.sstart_h.size(), st);
-}
+// Sides laid out one after the other, validated and in size order per side.
+struct Space {
+  std::vector<SideDesc> h_sides;
+  SideDesc *d_sides = nullptr;
+  uint32_t n_sides = 0;
+  uint64_t n = 0;                 // sets over all sides
+  uint32_t max_size = 0;          // over all sides
+  uint32_t stride = 2;            // group-start entries per side: max_size + 2
+  uint32_t seg_blocks = 0;        // workgroups of the segmented bitmap build
+  uint32_t *sizes = nullptr;      // size order, per side
+  uint32_t *perm = nullptr;       // size-order position -> caller index in the side
+  uint32_t *rank = nullptr;       // global caller position -> size-order position
+  uint32_t *side_of = nullptr;    // side of every global position
+  uint32_t *sstart = nullptr;     // [n_sides][stride]
+  std::vector<uint32_t> sstart_h;
+  std::vector<uint32_t> side_max; // largest size of each side
+  JoinCounters *ctr = nullptr;    // preparation counters
+  JoinCounters ctr_h{};
+  // bitmaps in size order, one array per width
+  uint32_t n_bm = 0;
+  uint32_t bm_words[kMaxClasses] = {0, 0, 0, 0};
+  uint64_t *bm[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
 
-// The bitmap widths of a join.  Each slot k holds the bitmaps of all sets in
-// size order at `words[k]` 64-bit words (b = 64 * words[k] bits, or the
-// caller's b padded to words[k]) at word offset off[k] of Side::bm.
-struct Widths {
-  uint32_t n = 0;
-  uint32_t words[4] = {0, 0, 0, 0};
-  uint32_t bits[4] = {0, 0, 0, 0};     // the width b the bitmaps are built for
-  uint64_t off[4] = {0, 0, 0, 0};
-  uint32_t slot_of(uint32_t w) const {
-    for (uint32_t k = 0; k < n; ++k)
-      if (words[k] == w) return k;
-    return 0;
+  const uint32_t *ss(uint32_t s) const { return sstart_h.data() + (size_t)s * stride; }
+  const uint64_t *bitmaps(uint32_t words) const {
+    for (uint32_t k = 0; k < n_bm; ++k)
+      if (bm_words[k] == words) return bm[k];
+    return nullptr;
   }
 };
 
-// Bitmap-Xor bitmaps of every slot (or the caller's, gathered and padded).
-// Token-order violations are reported in ctr->error.
-void build_bitmaps(Side &sd, const uint64_t *bm_caller, const Widths &wd, Arena &ar,
-                   JoinCounters *ctr, hipStream_t st) {
-  const uint64_t n = sd.n;
-  uint64_t total = 0;
-  for (uint32_t k = 0; k < wd.n; ++k) total = std::max(total, wd.off[k] + n * wd.words[k]);
-  sd.bm = ar.alloc<uint64_t>(total);
-  if (bm_caller) {  // one slot, the caller's width
-    check(launch_gather_bitmaps(bm_caller, sd.perm, n, wd.bits[0] / 64, wd.words[0],
-                                sd.bm + wd.off[0], st));
-    check(launch_check_sorted(sd.in->offsets, sd.in->tokens, n, ctr, st));
-    return;
+// Side table, sizes and offset checks of every side.  The caller
+// synchronises before space_sort (ctr_h holds the largest size).
+void space_begin(Space &sp, const ssj_sets *const *sides, uint32_t n_sides, Arena &ar,
+                 hipStream_t st) {
+  sp.n_sides = n_sides;
+  sp.h_sides.resize(n_sides);
+  uint64_t base = 0, blk = 0;
+  for (uint32_t s = 0; s < n_sides; ++s) {
+    validate_sets(sides[s]);
+    SideDesc &d = sp.h_sides[s];
+    d.offsets = sides[s]->offsets;
+    d.tokens = sides[s]->tokens;
+    d.n_tokens = sides[s]->n_tokens;
+    d.base = base;
+    d.n = (uint32_t)sides[s]->n_sets;
+    d.blk0 = (uint32_t)blk;
+    base += d.n;
+    blk += bitmap_seg_blocks(d.n);
   }
-  sd.rank = ar.alloc<uint32_t>(n);
-  check(launch_invert_perm(sd.perm, n, sd.rank, st));
-  for (uint32_t k = 0; k < wd.n; ++k)
-    check(launch_build_bitmaps(sd.in->offsets, sd.in->tokens, sd.perm, sd.rank, n, wd.bits[k],
-                               SSJ_BM_XOR, wd.words[k], sd.bm + wd.off[k], ctr, st));
+  if (base >= 0xFFFFFFFFull || blk >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
+  sp.n = base;
+  sp.seg_blocks = (uint32_t)blk;
+  sp.d_sides = ar.alloc<SideDesc>(n_sides);
+  h2d(sp.d_sides, sp.h_sides.data(), n_sides, st);
+  sp.ctr = ar.alloc<JoinCounters>(1);
+  check(launch_reset_all(sp.ctr, st));
+  sp.sizes = ar.alloc<uint32_t>(sp.n);
+  sp.side_of = ar.alloc<uint32_t>(sp.n);
+  check(launch_set_sizes(sp.d_sides, n_sides, sp.n, sp.sizes, sp.side_of, sp.ctr, st));
+  d2h(&sp.ctr_h, sp.ctr, 1, st);
 }
 
-// Least overlap o with sim >= p/q for sizes summing to L (Jaccard, Table 1):
-// o / (L - o) >= p / q  <=>  (p + q) o >= p L.
-inline uint32_t jaccard_omin(uint64_t L, uint64_t p, uint64_t q) {
-  return (uint32_t)((p * L + (p + q) - 1) / (p + q));
+// Stable sort by (side, size), group starts of every side (copied to the
+// host; the caller synchronises before space_finish), and the inverse
+// permutation when bitmaps are to be built.
+// Arrays the space keeps come from `ar`, the sort's temporaries from `tmp_ar`.
+void space_sort(Space &sp, bool need_rank, Arena &ar, Arena &tmp_ar, hipStream_t st) {
+  if (sp.ctr_h.error & (kErrOffsets | kErrTooBig)) throw Fail{SSJ_E_INVALID};
+  sp.max_size = sp.ctr_h.max_size;
+  if ((uint64_t)sp.max_size * 2 + 2 > kMaxTable) throw Fail{SSJ_E_UNSUPPORTED};
+  sp.stride = sp.max_size + 2;
+  const int size_bits = std::max(1, bits_for(sp.max_size));
+  const int side_bits = bits_for(sp.n_sides ? sp.n_sides - 1 : 0);
+  if (size_bits + side_bits > 32) throw Fail{SSJ_E_UNSUPPORTED};
+  const uint64_t n = sp.n;
+  sp.perm = ar.alloc<uint32_t>(n);
+  if (n) {
+    unsigned long long *keys = tmp_ar.alloc<unsigned long long>(n);
+    unsigned long long *tmp = tmp_ar.alloc<unsigned long long>(n);
+    uint32_t *scr = tmp_ar.alloc<uint32_t>(radix_scratch_words(n));
+    check(launch_make_keys(sp.d_sides, sp.sizes, sp.side_of, n, size_bits, keys, st));
+    int shifts[4], ns = 0;
+    for (int b = 0; b < size_bits + side_bits; b += 8) shifts[ns++] = 32 + b;
+    unsigned long long *sorted = keys;
+    check(radix_sort_u64(keys, tmp, n, shifts, ns, scr, st, &sorted));
+    check(launch_unpack_keys(sorted, n, size_bits, sp.sizes, sp.perm, st));
+  }
+  sp.sstart = ar.alloc<uint32_t>((uint64_t)sp.n_sides * sp.stride);
+  check(launch_group_starts(sp.d_sides, sp.sizes, sp.side_of, n, sp.max_size, sp.stride,
+                            sp.n_sides, sp.sstart, st));
+  if (need_rank) {
+    sp.rank = ar.alloc<uint32_t>(n);
+    check(launch_invert_perm(sp.d_sides, sp.perm, sp.side_of, n, sp.rank, st));
+  }
+  sp.sstart_h.assign((size_t)sp.n_sides * sp.stride, 0);
+  d2h(sp.sstart_h.data(), sp.sstart, sp.sstart_h.size(), st);
+}
+
+// Largest size of every side, from its group starts.
+void space_finish(Space &sp) {
+  sp.side_max.assign(sp.n_sides, 0);
+  for (uint32_t s = 0; s < sp.n_sides; ++s) {
+    const uint32_t *t = sp.ss(s);
+    const uint32_t n = sp.h_sides[s].n;
+    uint32_t m = 0;
+    for (uint32_t v = 1; v <= sp.max_size; ++v)
+      if (t[v] < n) m = v;
+    sp.side_max[s] = m;
+  }
+}
+
+// Bitmap-Xor bitmaps of every set at `words` 64-bit words (nominal width
+// `bits`), in size order.
+void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCounters *ctr,
+                   hipStream_t st) {
+  if (sp.bitmaps(words)) return;
+  if (sp.n_bm >= kMaxClasses) throw Fail{SSJ_E_DEVICE};
+  uint64_t *out = ar.alloc<uint64_t>(sp.n * words);
+  check(launch_build_bitmaps(sp.d_sides, sp.n_sides, sp.seg_blocks, sp.n, sp.perm, sp.rank,
+                             sp.side_of, bits, SSJ_BM_XOR, words, out, ctr, st));
+  sp.bm_words[sp.n_bm] = words;
+  sp.bm[sp.n_bm] = out;
+  ++sp.n_bm;
+}
+
+// The caller's bitmaps of a one-side space (caller order, bits/64 words),
+// gathered into size order and padded to `words`.
+void space_caller_bitmaps(Space &sp, const uint64_t *bm_caller, uint32_t words, uint32_t bits,
+                          Arena &ar, JoinCounters *ctr, hipStream_t st) {
+  uint64_t *out = ar.alloc<uint64_t>(sp.n * words);
+  check(launch_gather_bitmaps(bm_caller, sp.perm, sp.n, bits / 64, words, out, st));
+  check(launch_check_sorted(sp.h_sides[0].offsets, sp.h_sides[0].tokens, sp.n, ctr, st));
+  sp.bm_words[0] = words;
+  sp.bm[0] = out;
+  sp.n_bm = 1;
+}
+
+// ------------------------------------------------------------- thresholds
+inline uint64_t ceil_div(uint64_t x, uint64_t y) { return (x + y - 1) / y; }
+
+// Least overlap o with sim >= p/q (Table 1, integer forms) for the
+// functions where it depends on L = |r| + |s| only:
+//   Jaccard  o / (L - o) >= p / q  <=>  (p + q) o >= p L
+//   Dice     2 o / L >= p / q      <=>  2 q o >= p L
+//   Overlap  o >= p / q            <=>  q o >= p
+inline uint32_t omin_of_sum(int sim, uint64_t L, uint64_t p, uint64_t q) {
+  switch (sim) {
+    case SSJ_SIM_DICE: return (uint32_t)ceil_div(p * L, 2 * q);
+    case SSJ_SIM_OVERLAP: return (uint32_t)ceil_div(p, q);
+    default: return (uint32_t)ceil_div(p * L, p + q);
+  }
+}
+
+// Least overlap for row size a and column size c, any function.
+inline uint32_t omin_of(int sim, uint64_t a, uint64_t c, uint64_t p, uint64_t q) {
+  if (sim == SSJ_SIM_COSINE) return cosine_omin((uint32_t)a, (uint32_t)c, (uint32_t)p, (uint32_t)q);
+  return omin_of_sum(sim, a + c, p, q);
+}
+
+// Column sizes [lo, hi] that can reach the threshold with a row of size
+// a >= 1 (Table 2: the best case o = min(|r|, |s|), solved for |s|):
+//   Jaccard  p a / q <= c <= q a / p
+//   Dice     p a / (2q - p) <= c <= (2q - p) a / p
+//   Cosine   p^2 a / q^2 <= c <= q^2 a / p^2
+//   Overlap  c >= p / q when a >= p / q; nothing otherwise
+void size_band(int sim, uint64_t a, uint64_t p, uint64_t q, uint64_t &lo, uint64_t &hi) {
+  typedef unsigned __int128 u128;
+  auto clamp = [](u128 v) { return v > (u128)UINT64_MAX ? UINT64_MAX : (uint64_t)v; };
+  switch (sim) {
+    case SSJ_SIM_DICE:
+      lo = ceil_div(p * a, 2 * q - p);
+      hi = (2 * q - p) * a / p;
+      break;
+    case SSJ_SIM_COSINE: {
+      const u128 pp = (u128)p * p, qq = (u128)q * q;
+      lo = clamp((pp * a + qq - 1) / qq);
+      hi = clamp(qq * a / pp);
+      break;
+    }
+    case SSJ_SIM_OVERLAP: {
+      const uint64_t o = ceil_div(p, q);
+      if (a < o) {
+        lo = UINT64_MAX;
+        hi = 0;
+      } else {
+        lo = o;
+        hi = UINT64_MAX;
+      }
+      break;
+    }
+    default:
+      lo = ceil_div(p * a, q);
+      hi = q * a / p;
+      break;
+  }
+  lo = std::max<uint64_t>(lo, 1);
 }
 
 // P(X <= k) for X ~ Binomial(n, pi), summed in log space.
@@ -270,114 +409,166 @@ struct WidthClass {
   uint32_t words;
 };
 
-std::vector<WidthClass> choose_classes(uint32_t max_rows, uint64_t p, uint64_t q) {
-  std::vector<WidthClass> cls;
-  uint32_t cur = 1;
-  for (uint32_t a = 1; a <= max_rows; ++a) {
-    const uint64_t L = 2ull * a;
-    const int64_t slack = (int64_t)L - 2 * (int64_t)jaccard_omin(L, p, q);
-    uint32_t best = cur;
-    double best_cost = 1e300;
-    for (uint32_t w : kAutoWords) {
-      if (w < cur) continue;
-      const double b = 64.0 * w;
-      const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
-      const double cost = (b / 16 + 1) + binomial_cdf((int)b, pi, slack) * kSurvivorCost;
-      if (cost < best_cost) {
-        best_cost = cost;
-        best = w;
+// The width of every row size up to max_rows, in classes of consecutive
+// sizes.  The per-size choice depends only on the threshold, so it is kept
+// per threshold and extended as larger sizes come up.
+std::vector<WidthClass> choose_classes(uint32_t max_rows, int sim, uint64_t p, uint64_t q) {
+  static std::mutex mu;
+  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>, std::vector<uint8_t>> memo;
+  std::vector<uint8_t> wa;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<uint8_t> &w = memo[{sim, {p, q}}];  // w[a]: words for row size a; w[0] unused
+    if (w.empty()) w.push_back((uint8_t)kAutoWords[0]);
+    uint32_t cur = w.back();
+    const uint32_t upto = std::max<uint32_t>(max_rows, 1);
+    for (uint32_t a = (uint32_t)w.size(); a <= upto; ++a) {
+      if (cur != kAutoWords[3]) {
+        const uint64_t L = 2ull * a;
+        const int64_t slack = (int64_t)L - 2 * (int64_t)omin_of(sim, a, a, p, q);
+        uint32_t best = cur;
+        double best_cost = 1e300;
+        for (uint32_t wd : kAutoWords) {
+          if (wd < cur) continue;
+          const double b = 64.0 * wd;
+          const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
+          const double cost = (b / 16 + 1) + binomial_cdf((int)b, pi, slack) * kSurvivorCost;
+          if (cost < best_cost) {
+            best_cost = cost;
+            best = wd;
+          }
+        }
+        cur = best;
       }
+      w.push_back((uint8_t)cur);
     }
-    cur = best;
-    if (!cls.empty() && cls.back().words == cur) cls.back().max_size = a;
-    else cls.push_back({a, cur});
+    wa.assign(w.begin(), w.begin() + upto + 1);
   }
-  if (cls.empty()) cls.push_back({max_rows, kAutoWords[0]});
+  std::vector<WidthClass> cls;
+  for (uint32_t a = 1; a <= max_rows; ++a) {
+    if (!cls.empty() && cls.back().words == wa[a]) cls.back().max_size = a;
+    else cls.push_back({a, wa[a]});
+  }
+  if (cls.empty()) cls.push_back({max_rows, wa[1]});
   cls.back().max_size = max_rows;
   return cls;
 }
 
+// ------------------------------------------------------------------- plan
+
+// One task of a call, as planned on the host (p/q reduced).
+struct TaskIn {
+  uint32_t row_side;
+  uint32_t col_side;
+  int sim;
+  uint32_t p, q;
+  bool self;
+};
+
 struct Plan {
-  std::vector<int32_t> slack;   // [maxA + maxB + 1]
-  std::vector<uint32_t> omin;   // [maxA + maxB + 1]
-  std::vector<uint32_t> cmin, cmax;  // [maxA + 1]
+  std::vector<uint32_t> tables;  // slack / omin / cmin / cmax of every task
+  std::vector<TaskDesc> tasks;
   std::vector<RowBlock> blocks;
   uint32_t n_tiles = 0;
   uint64_t band_pairs = 0;
-  uint64_t filter_ops = 0;      // sum over band pairs of b/16 + 1
-  uint32_t max_batch = 0;       // largest queue reservation of the kernels used
-  // per width class: its tiles [tile_lo[k], tile_hi[k]) and padded width
-  uint32_t n_classes = 0;
+  uint64_t filter_ops = 0;       // sum over band pairs of b/16 + 1
+  uint32_t max_batch = 0;        // largest queue reservation of the kernels used
+  // per width slot: its tiles [tile_lo[k], tile_hi[k]), padded width, work
+  uint32_t n_slots = 0;
+  uint32_t slot_words[kMaxClasses] = {0, 0, 0, 0};
+  uint32_t slot_bits[kMaxClasses] = {0, 0, 0, 0};
+  uint32_t slot_max_size[kMaxClasses] = {0, 0, 0, 0};
   uint32_t tile_lo[kMaxClasses] = {0, 0, 0, 0}, tile_hi[kMaxClasses] = {0, 0, 0, 0};
-  uint32_t words[kMaxClasses] = {0, 0, 0, 0};
   uint64_t ops[kMaxClasses] = {0, 0, 0, 0};
 };
 
-void make_tables(Plan &pl, const Side &A, const Side &B, uint64_t p, uint64_t q) {
-  const uint64_t maxA = A.max_size, maxB = B.max_size;
-  pl.slack.resize(maxA + maxB + 1);
-  pl.omin.resize(maxA + maxB + 1);
-  for (uint64_t L = 0; L <= maxA + maxB; ++L) {
-    uint32_t o = jaccard_omin(L, p, q);
-    pl.omin[L] = o;
-    pl.slack[L] = (int32_t)((int64_t)L - 2 * (int64_t)o);
+// The task's threshold tables, appended to pl.tables.
+void add_tables(Plan &pl, TaskDesc &td, uint64_t a_max, uint64_t c_max, int sim, uint64_t p,
+                uint64_t q) {
+  const uint64_t nL = sim == SSJ_SIM_COSINE ? 1 : a_max + c_max + 1, nA = a_max + 1;
+  if (pl.tables.size() + 2 * nL + 2 * nA >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
+  // slack[L] = L - 2 omin(L); Cosine's depend on both sizes and are computed
+  // where they are needed, its tables are one unused entry each
+  td.slack_off = (uint32_t)pl.tables.size();
+  for (uint64_t L = 0; L < nL; ++L)
+    pl.tables.push_back(
+        (uint32_t)(int32_t)((int64_t)L - 2 * (int64_t)omin_of_sum(sim, L, p, q)));
+  td.omin_off = (uint32_t)pl.tables.size();
+  for (uint64_t L = 0; L < nL; ++L) pl.tables.push_back(omin_of_sum(sim, L, p, q));
+  // length filter; empty sets never pair: an empty row gets an empty range,
+  // and cmin >= 1 otherwise
+  td.cmin_off = (uint32_t)pl.tables.size();
+  pl.tables.resize(pl.tables.size() + 2 * nA);
+  td.cmax_off = td.cmin_off + (uint32_t)nA;
+  for (uint64_t a = 0; a < nA; ++a) {
+    uint64_t lo = UINT64_MAX, hi = 0;
+    if (a) size_band(sim, a, p, q, lo, hi);
+    pl.tables[td.cmin_off + a] = (uint32_t)std::min<uint64_t>(lo, 0xFFFFFFFFull);
+    pl.tables[td.cmax_off + a] = (uint32_t)std::min<uint64_t>(hi, 0xFFFFFFFFull);
   }
-  // Length filter (Table 2, Jaccard): t |r| <= |s| <= |r| / t.  Empty sets
-  // never pair: an empty row gets an empty range, and cmin >= 1 otherwise.
-  pl.cmin.resize(maxA + 1);
-  pl.cmax.resize(maxA + 1);
-  for (uint64_t a = 0; a <= maxA; ++a) {
-    if (a == 0) {
-      pl.cmin[a] = 0xFFFFFFFFu;
-      pl.cmax[a] = 0;
-      continue;
-    }
-    uint64_t lo = (p * a + q - 1) / q;   // ceil(p a / q)
-    uint64_t hi = (q * a) / p;           // floor(q a / p)
-    if (lo < 1) lo = 1;
-    pl.cmin[a] = (uint32_t)std::min<uint64_t>(lo, 0xFFFFFFFFull);
-    pl.cmax[a] = (uint32_t)std::min<uint64_t>(hi, 0xFFFFFFFFull);
-  }
+  td.sim = (uint32_t)sim;
+  td.p = (uint32_t)p;
+  td.q = (uint32_t)q;
+  td.pad = 0;
+  (void)c_max;
 }
 
-// Row blocks and tiles of the length band.  Rows of size in (lo, hi] use
-// `words`-word bitmaps of nominal width `bits`; blocks never straddle classes.
-void plan_class(Plan &pl, const Side &A, const Side &B, bool self, uint32_t lo, uint32_t hi,
-                uint32_t words, uint32_t bits, uint32_t tile_cols) {
-  const uint64_t maxA = A.max_size, maxB = B.max_size;
+// Row blocks and tiles of one task's length band for its rows of size in
+// (lo, hi], which use `words`-word bitmaps of nominal width `bits`; blocks
+// never straddle width classes.
+void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint32_t task_id,
+                uint32_t lo, uint32_t hi, uint32_t words, uint32_t bits, uint32_t tile_cols,
+                uint64_t &band_out) {
+  const TaskDesc &td = pl.tasks[task_id];
+  const uint32_t *rs = R.ss(tk.row_side), *cs = C.ss(tk.col_side);
+  const uint64_t a_max = R.side_max[tk.row_side], c_max = C.side_max[tk.col_side];
+  const uint32_t col_n = C.h_sides[tk.col_side].n;
+  const uint32_t row_base = (uint32_t)R.h_sides[tk.row_side].base;
+  const uint32_t col_base = (uint32_t)C.h_sides[tk.col_side].base;
+  const uint32_t *cmin = pl.tables.data() + td.cmin_off;
+  const uint32_t *cmax = pl.tables.data() + td.cmax_off;
   const FilterShape shape = filter_shape(words);
   pl.max_batch = std::max(pl.max_batch, shape.batch);
   auto col_lo = [&](uint64_t a) -> uint32_t {  // first column with size >= cmin[a]
-    uint64_t c = pl.cmin[a];
-    return c > maxB ? (uint32_t)B.n : B.sstart_h[c];
+    const uint64_t c = cmin[a];
+    return c > c_max ? col_n : cs[c];
   };
   auto col_hi = [&](uint64_t a) -> uint32_t {  // first column with size > cmax[a]
-    uint64_t c = pl.cmax[a];
-    return c >= maxB ? (uint32_t)B.n : B.sstart_h[c + 1];
+    const uint64_t c = cmax[a];
+    return c >= c_max ? col_n : cs[c + 1];
   };
-  hi = (uint32_t)std::min<uint64_t>(hi, maxA);
+  hi = (uint32_t)std::min<uint64_t>(hi, a_max);
+  if (lo >= hi) return;
+  // Sizes whose band is empty (Overlap: below ceil(p/q)) come first; the
+  // class's row blocks start after them, so that every block's column range,
+  // taken from its smallest size, is that of a size that pairs.
+  auto empty_band = [&](uint64_t a) {
+    return cmin[a] > cmax[a] || (tk.self && cmin[a] > a);
+  };
+  while (lo < hi && empty_band(lo + 1)) ++lo;
   if (lo >= hi) return;
   // band pairs of the class, exactly
   uint64_t band = 0;
   for (uint64_t a = lo + 1; a <= hi; ++a) {
-    uint64_t cnt = A.count_of((uint32_t)a);
-    if (!cnt) continue;
-    if (self) {
-      band += cnt * ((uint64_t)A.sstart_h[a] - col_lo(a)) + cnt * (cnt - 1) / 2;
+    const uint64_t cnt = (uint64_t)rs[a + 1] - rs[a];
+    if (!cnt || empty_band(a)) continue;
+    if (tk.self) {
+      band += cnt * ((uint64_t)rs[a] - col_lo(a)) + cnt * (cnt - 1) / 2;
     } else {
-      uint64_t l = col_lo(a), h = col_hi(a);
+      const uint64_t l = col_lo(a), h = col_hi(a);
       if (h > l) band += cnt * (h - l);
     }
   }
+  band_out += band;
   pl.band_pairs += band;
   pl.filter_ops += band * (bits / 16 + 1);
 
   const uint32_t rows_per_block = shape.rows;
-  const uint32_t r_begin = A.sstart_h[lo + 1], r_end = A.sstart_h[hi + 1];
+  const uint32_t r_begin = rs[lo + 1], r_end = rs[hi + 1];
   uint64_t tiles = pl.n_tiles;
   uint32_t s_of = lo + 1;  // size of the current row, advanced monotonically
   auto size_at = [&](uint32_t row) {
-    while (s_of + 1 <= hi && A.sstart_h[s_of + 1] <= row) ++s_of;
+    while (s_of + 1 <= hi && rs[s_of + 1] <= row) ++s_of;
     return s_of;
   };
   for (uint64_t r0 = r_begin; r0 < r_end; r0 += rows_per_block) {
@@ -385,22 +576,26 @@ void plan_class(Plan &pl, const Side &A, const Side &B, bool self, uint32_t lo, 
     const uint32_t row_end = (uint32_t)std::min<uint64_t>(r0 + rows_per_block, r_end);
     const uint32_t a0 = size_at(row0);
     RowBlock rb{};
-    rb.row0 = row0;
-    rb.row_end = row_end;
-    rb.words = words;
+    rb.row0 = row_base + row0;
+    rb.row_end = row_base + row_end;
     rb.tile_begin = (uint32_t)tiles;
+    rb.task = task_id;
+    rb.self = tk.self ? 1u : 0u;
     uint64_t nt;
-    if (self) {
-      rb.col_begin = std::min(col_lo(a0), row0);
-      rb.col_end = row_end;
-      nt = ((uint64_t)row0 - rb.col_begin + tile_cols - 1) / tile_cols + 1;
+    if (tk.self) {
+      const uint32_t cb = std::min(col_lo(a0), row0);
+      rb.col_begin = col_base + cb;
+      rb.col_end = col_base + row_end;
+      nt = ((uint64_t)row0 - cb + tile_cols - 1) / tile_cols + 1;
     } else {
       const uint32_t s_save = s_of;
       const uint32_t a1 = size_at(row_end - 1);  // the block's largest size
       s_of = s_save;
-      rb.col_begin = col_lo(a0);
-      rb.col_end = std::max(col_hi(a1), rb.col_begin);
-      nt = ((uint64_t)rb.col_end - rb.col_begin + tile_cols - 1) / tile_cols;
+      const uint32_t cb = col_lo(a0);
+      const uint32_t ce = std::max(col_hi(a1), cb);
+      rb.col_begin = col_base + cb;
+      rb.col_end = col_base + ce;
+      nt = ((uint64_t)ce - cb + tile_cols - 1) / tile_cols;
     }
     tiles += nt;
     if (tiles >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
@@ -428,259 +623,400 @@ struct Timer {
   }
 };
 
-int join(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint64_t *s_bm,
-         bool self, uint32_t b_bits, int sim, uint32_t p, uint32_t q, const ssj_options *opts,
-         ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
-  const auto t_start = std::chrono::steady_clock::now();
-  if (!out) return SSJ_E_INVALID;
+
+// ------------------------------------------------------------------- join
+
+struct JoinOut {
+  ssj_pair *pairs = nullptr;            // host, malloc
+  uint64_t count = 0;
+  std::vector<uint64_t> task_start;     // [n_tasks + 1]
+};
+
+struct JoinConfig {
+  uint32_t b_bits = 0;         // 0: width classes chosen per task
+  uint32_t tile_cols = kDefaultTileCols;
+  uint64_t cap = kDefaultQueue;
+  bool survivors_only = false;
+  bool cols_resident = false;  // the column space is an index's: no bitmaps are added to it
+};
+
+// Plans and runs the tasks over prepared spaces R (rows) and C (columns; C
+// may be R), whose caller bitmaps, if any, are already in place.  Fills jo
+// and the stats (except ms_total and ms_prepare's start).
+void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinConfig &jc,
+              Arena &ar, JoinCounters *ctr, hipStream_t st, Timer &t_prep, JoinOut &jo,
+              ssj_stats *stats) {
+  const bool automatic = jc.b_bits == 0;
+  const uint32_t n_tasks = (uint32_t)tasks.size();
+  Plan pl;
+  pl.tasks.resize(n_tasks);
+  std::vector<std::vector<WidthClass>> classes(n_tasks);
+  std::vector<uint64_t> task_band(n_tasks, 0);
+  std::vector<uint32_t> side_task(R.n_sides, 0xFFFFFFFFu);
+  const uint32_t wpad = automatic ? 0 : filter_padded_words(jc.b_bits / 64);
+  if (!automatic && !wpad) throw Fail{SSJ_E_UNSUPPORTED};
+  for (uint32_t k = 0; k < n_tasks; ++k) {
+    const TaskIn &tk = tasks[k];
+    if (side_task[tk.row_side] != 0xFFFFFFFFu) throw Fail{SSJ_E_INVALID};
+    side_task[tk.row_side] = k;
+    TaskDesc &td = pl.tasks[k];
+    const uint32_t a_max = R.side_max[tk.row_side], c_max = C.side_max[tk.col_side];
+    add_tables(pl, td, a_max, c_max, tk.sim, tk.p, tk.q);
+    td.row_side = tk.row_side;
+    td.col_side = tk.col_side;
+    td.col_base = (uint32_t)C.h_sides[tk.col_side].base;
+    td.self = tk.self ? 1u : 0u;
+    td.col_sstart_off = (uint64_t)tk.col_side * C.stride;
+    if (automatic)
+      classes[k] = choose_classes(std::max<uint32_t>(a_max, 1), tk.sim, tk.p, tk.q);
+    else classes[k].push_back({a_max, wpad});
+  }
+  bool any_cosine = false;
+  for (const auto &tk : tasks) any_cosine |= tk.sim == SSJ_SIM_COSINE;
+  // width slots: every width some task uses, narrowest first
+  if (automatic) {
+    for (uint32_t w : kAutoWords) {
+      bool used = false;
+      for (auto &cl : classes)
+        for (auto &c : cl) used |= c.words == w;
+      if (!used) continue;
+      pl.slot_words[pl.n_slots] = w;
+      pl.slot_bits[pl.n_slots] = 64 * w;
+      ++pl.n_slots;
+    }
+  } else if (n_tasks) {
+    pl.slot_words[0] = wpad;
+    pl.slot_bits[0] = jc.b_bits;
+    pl.n_slots = 1;
+  }
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    if (!R.bitmaps(pl.slot_words[k])) space_bitmaps(R, pl.slot_words[k], pl.slot_bits[k], ar, ctr, st);
+    if (!C.bitmaps(pl.slot_words[k])) {
+      if (jc.cols_resident) throw Fail{SSJ_E_UNSUPPORTED};
+      space_bitmaps(C, pl.slot_words[k], pl.slot_bits[k], ar, ctr, st);
+    }
+  }
+  // tiles, slot by slot, task by task
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    pl.tile_lo[k] = pl.n_tiles;
+    const uint64_t ops0 = pl.filter_ops;
+    for (uint32_t t = 0; t < n_tasks; ++t) {
+      uint32_t prev = 0;
+      for (auto &c : classes[t]) {
+        if (c.words == pl.slot_words[k]) {
+          plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
+                     jc.tile_cols, task_band[t]);
+          pl.slot_max_size[k] = std::max(pl.slot_max_size[k], c.max_size);
+        }
+        prev = c.max_size;
+      }
+    }
+    pl.tile_hi[k] = pl.n_tiles;
+    pl.ops[k] = pl.filter_ops - ops0;
+  }
+
+  // blocks, tasks, the row sides' tasks and the tables go up in one copy
+  constexpr uint64_t kBlockWords = sizeof(RowBlock) / 4, kTaskWords = sizeof(TaskDesc) / 4;
+  static_assert(sizeof(RowBlock) % 8 == 0 && sizeof(TaskDesc) % 8 == 0, "8-byte layout");
+  const uint64_t nB = pl.blocks.size(), nT = pl.tasks.size(), nS = side_task.size();
+  std::vector<uint32_t> packed(kBlockWords * nB + kTaskWords * nT + nS + pl.tables.size());
+  uint32_t *hp = packed.data();
+  std::memcpy(hp, pl.blocks.data(), nB * sizeof(RowBlock));
+  std::memcpy(hp + kBlockWords * nB, pl.tasks.data(), nT * sizeof(TaskDesc));
+  std::memcpy(hp + kBlockWords * nB + kTaskWords * nT, side_task.data(), nS * 4);
+  std::memcpy(hp + kBlockWords * nB + kTaskWords * nT + nS, pl.tables.data(),
+              pl.tables.size() * 4);
+  uint32_t *d_packed = ar.alloc<uint32_t>(packed.size());
+  h2d(d_packed, packed.data(), packed.size(), st);
+  const RowBlock *d_blocks = reinterpret_cast<const RowBlock *>(d_packed);
+  const TaskDesc *d_tasks = reinterpret_cast<const TaskDesc *>(d_packed + kBlockWords * nB);
+  const uint32_t *d_side_task = d_packed + kBlockWords * nB + kTaskWords * nT;
+  const uint32_t *d_tables = d_side_task + nS;
+  uint32_t *d_tile_block = ar.alloc<uint32_t>(pl.n_tiles);
+  check(launch_expand_tiles(d_blocks, (uint32_t)nB, pl.n_tiles, d_tile_block, st));
+  check(hipEventRecord(t_prep.ev[1], st));
+
+  // filter / verify rounds.  A queue reservation covers one step of U
+  // columns for all of a wave's rows; the queue must hold the largest such
+  // batch, or a full step could never be written and its tile never resumed.
+  const uint64_t qcap = std::max<uint64_t>(std::max<uint64_t>(pl.max_batch, 4096),
+                                           std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
+  uint2 *queue = ar.alloc<uint2>(qcap);
+  const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
+  Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
+  uint64_t res_cap = std::max<uint64_t>(qcap, 1024);
+  unsigned long long *results = ar.alloc<unsigned long long>(res_cap);
+  int ib = 1, jb = 1;
+  for (const auto &d : R.h_sides) ib = std::max(ib, bits_for(d.n ? d.n - 1 : 0));
+  for (const auto &d : C.h_sides) jb = std::max(jb, bits_for(d.n ? d.n - 1 : 0));
+  const int tb = bits_for(n_tasks > 1 ? n_tasks - 1 : 0);
+  if (tb + ib + jb > 64) throw Fail{SSJ_E_UNSUPPORTED};
+  const VerifySpace vrows{R.d_sides, R.side_of, R.perm, (uint32_t)R.n};
+  const VerifySpace vcols{C.d_sides, C.side_of, C.perm, (uint32_t)C.n};
+
+  std::deque<Timer> t_filter, t_verify;  // events must not move
+  std::vector<uint32_t> t_filter_slot;
+  uint32_t n_resume_in = 0;
+  uint64_t results_n = 0;
+  JoinCounters ctr_h{};
+  FilterConfig cfg{};
+  cfg.n_rows = (uint32_t)R.n;
+  cfg.n_cols = (uint32_t)C.n;
+  cfg.n_tiles = pl.n_tiles;
+  cfg.tile_cols = jc.tile_cols;
+  cfg.n_blocks = (uint32_t)nB;
+  cfg.resume_cap = max_waves;
+  cfg.cap = qcap;
+  for (;;) {
+    if (pl.n_tiles == 0) break;
+    cfg.n_resume_in = n_resume_in;
+    // one launch per width slot; after an overflow the later launches of
+    // the round leave at once and resume in the next round
+    for (uint32_t k = 0; k < pl.n_slots; ++k) {
+      if (pl.tile_hi[k] == pl.tile_lo[k]) continue;
+      cfg.tile_lo = pl.tile_lo[k];
+      cfg.tile_hi = pl.tile_hi[k];
+      cfg.cls = k;
+      const uint32_t w = pl.slot_words[k];
+      FilterArgs fa{R.bitmaps(w), C.bitmaps(w), R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
+                    d_blocks, d_tile_block, queue, ctr, res_a, res_b, cfg};
+      t_filter.emplace_back();
+      t_filter_slot.push_back(k);
+      check(hipEventRecord(t_filter.back().ev[0], st));
+      check(launch_filter(w, any_cosine, fa, st));
+      check(hipEventRecord(t_filter.back().ev[1], st));
+    }
+    t_verify.emplace_back();
+    check(hipEventRecord(t_verify.back().ev[0], st));
+    check(launch_verify(queue, qcap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
+                        jc.survivors_only ? 1u : 0u, results, res_cap, ctr, st));
+    check(hipEventRecord(t_verify.back().ev[1], st));
+    d2h(&ctr_h, ctr, 1, st);
+    sync(st);
+    if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+    results_n = ctr_h.results;
+    if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
+    if (!ctr_h.overflow) break;
+    // drain done; make room for another full queue of results, then resume
+    if (results_n + qcap > res_cap) {
+      const uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
+      unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
+      check(launch_copy_u64(results, results_n, nr, st));
+      results = nr;
+      res_cap = ncap;
+    }
+    n_resume_in = ctr_h.n_resume;
+    std::swap(res_a, res_b);
+    check(launch_reset_round(ctr, st));
+  }
+  if (pl.n_tiles == 0) {
+    // nothing to filter; still report unsorted input
+    d2h(&ctr_h, ctr, 1, st);
+    sync(st);
+    if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+  }
+
+  // emit: sort the keys (task, i, j) on all their digits, split, copy out
+  Timer t_emit;
+  check(hipEventRecord(t_emit.ev[0], st));
+  jo.task_start.assign(n_tasks + 1, 0);
+  if (results_n) {
+    unsigned long long *tmp = ar.alloc<unsigned long long>(results_n);
+    uint32_t *scr = ar.alloc<uint32_t>(radix_scratch_words(results_n));
+    int shifts[8], ns = 0;
+    for (int b = 0; b < tb + ib + jb; b += 8) shifts[ns++] = b;
+    unsigned long long *sorted = results;
+    check(radix_sort_u64(results, tmp, results_n, shifts, ns, scr, st, &sorted));
+    ssj_pair *dpairs = ar.alloc<ssj_pair>(results_n);
+    uint64_t *dstart = ar.alloc<uint64_t>(n_tasks + 1);
+    check(launch_split_results(sorted, results_n, ib, jb, n_tasks, dpairs, dstart, st));
+    jo.pairs = static_cast<ssj_pair *>(std::malloc(results_n * sizeof(ssj_pair)));
+    if (!jo.pairs) throw Fail{SSJ_E_NOMEM};
+    jo.count = results_n;
+    d2h(jo.pairs, dpairs, results_n, st);
+    d2h(jo.task_start.data(), dstart, n_tasks + 1, st);
+  }
+  check(hipEventRecord(t_emit.ev[1], st));
+  sync(st);
+  if (stats) {
+    stats->band_pairs = pl.band_pairs;
+    stats->survivors = ctr_h.survivors;
+    stats->results = results_n;
+    stats->filter_launches = (uint32_t)t_filter.size();
+    stats->b_bits = jc.b_bits;
+    stats->filter_ops = pl.filter_ops;
+    stats->n_classes = pl.n_slots;
+    for (uint32_t k = 0; k < pl.n_slots; ++k) {
+      stats->class_bits[k] = pl.slot_bits[k];
+      stats->class_max_size[k] = pl.slot_max_size[k];
+      stats->class_ops[k] = pl.ops[k];
+    }
+    stats->ms_prepare = t_prep.ms();
+    for (size_t k = 0; k < t_filter.size(); ++k) {
+      const float ms = t_filter[k].ms();
+      stats->ms_filter += ms;
+      stats->class_ms[t_filter_slot[k]] += ms;
+    }
+    for (auto &t : t_verify) stats->ms_verify += t.ms();
+    stats->ms_emit = t_emit.ms();
+  }
+}
+
+// Checks and reduces a threshold: 1 <= p <= q, except Overlap (o >= p/q),
+// which takes any p >= 1.
+void check_threshold(int sim, uint32_t &p, uint32_t &q) {
+  if (sim < SSJ_SIM_JACCARD || sim > SSJ_SIM_OVERLAP) throw Fail{SSJ_E_INVALID};
+  if (p == 0 || q == 0 || (p > q && sim != SSJ_SIM_OVERLAP)) throw Fail{SSJ_E_INVALID};
+  const uint32_t g = std::gcd(p, q);
+  p /= g;
+  q /= g;
+}
+
+JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
+  if (b_bits != 0 && (b_bits < 64 || b_bits > 4096 || b_bits % 64)) throw Fail{SSJ_E_INVALID};
+  JoinConfig jc;
+  jc.b_bits = b_bits;
+  if (opts && opts->tile_cols) jc.tile_cols = opts->tile_cols;
+  if (opts && opts->queue_capacity) jc.cap = opts->queue_capacity;
+  jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
+  return jc;
+}
+
+void clear_out(ssj_pairs *out, ssj_stats *stats) {
   out->pairs = nullptr;
   out->count = 0;
   if (stats) std::memset(stats, 0, sizeof(*stats));
-  try {
-    validate_sets(R);
-    if (!self) validate_sets(S);
-    const bool automatic = b_bits == 0;
-    if (!automatic && (b_bits < 64 || b_bits > 4096 || b_bits % 64)) return SSJ_E_INVALID;
-    if (automatic && (r_bm || s_bm)) return SSJ_E_INVALID;
-    if (sim < SSJ_SIM_JACCARD || sim > SSJ_SIM_OVERLAP) return SSJ_E_INVALID;
-    if (p == 0 || q == 0 || p > q) return SSJ_E_INVALID;
-    if (sim != SSJ_SIM_JACCARD) return SSJ_E_UNSUPPORTED;
-    const uint32_t g = std::gcd(p, q);
-    p /= g;
-    q /= g;
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const uint32_t tile_cols = opts && opts->tile_cols ? opts->tile_cols : kDefaultTileCols;
-    const uint64_t cap = opts && opts->queue_capacity ? opts->queue_capacity : kDefaultQueue;
-    const bool survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
+}
 
+float ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ssj_self_join / ssj_rs_join: one task, each side in its own space (the
+// self-join's row and column space are one).
+int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint64_t *s_bm,
+             bool self, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
+             const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!out) return SSJ_E_INVALID;
+  clear_out(out, stats);
+  JoinOut jo;
+  try {
+    const JoinConfig jc = config_of(b_bits, opts);
+    if (b_bits == 0 && (r_bm || s_bm)) return SSJ_E_INVALID;
+    check_threshold(sim, p, q);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Arena ar(st);
-    Timer t_prep, t_emit;
+    Timer t_prep;
     check(hipEventRecord(t_prep.ev[0], st));
     JoinCounters *ctr = ar.alloc<JoinCounters>(1);
-    JoinCounters ctr_h;
     check(launch_reset_all(ctr, st));
-
-    Side A, B;
-    order(A, R, ar, st);
-    if (!self) order(B, S, ar, st);
-    sync(st);  // group starts on the host
-    const Side &Bc = self ? A : B;
-
-    // bitmap widths: one fixed width, or classes of row sizes
-    Widths wd;
-    std::vector<WidthClass> classes;
-    if (automatic) {
-      classes = choose_classes(std::max<uint32_t>(A.max_size, 1), p, q);
-      for (uint32_t w : kAutoWords) {
-        bool used = false;
-        for (auto &c : classes) used |= c.words == w;
-        if (!used) continue;
-        wd.words[wd.n] = w;
-        wd.bits[wd.n] = 64 * w;
-        ++wd.n;
-      }
-    } else {
-      const uint32_t wpad = filter_padded_words(b_bits / 64);
-      if (!wpad) return SSJ_E_UNSUPPORTED;
-      wd.n = 1;
-      wd.words[0] = wpad;
-      wd.bits[0] = b_bits;
-      classes.push_back({A.max_size, wpad});
-    }
-    if (classes.size() > kMaxClasses) throw Fail{SSJ_E_DEVICE};
-    uint64_t o_a = 0, o_b = 0;
-    for (uint32_t k = 0; k < wd.n; ++k) {
-      wd.off[k] = o_a;
-      o_a += A.n * wd.words[k];
-    }
-    Widths wd_b = wd;
-    for (uint32_t k = 0; k < wd.n; ++k) {
-      wd_b.off[k] = o_b;
-      o_b += Bc.n * wd.words[k];
-    }
-    build_bitmaps(A, r_bm, wd, ar, ctr, st);
-    if (!self) build_bitmaps(B, s_bm, wd_b, ar, ctr, st);
-
-    Plan pl;
-    make_tables(pl, A, Bc, p, q);
-    uint32_t prev = 0;
-    for (auto &c : classes) {
-      const uint32_t bits = automatic ? 64 * c.words : b_bits;
-      const uint32_t k = pl.n_classes++;
-      pl.tile_lo[k] = pl.n_tiles;
-      pl.words[k] = c.words;
-      const uint64_t ops0 = pl.filter_ops;
-      plan_class(pl, A, Bc, self, prev, c.max_size, c.words, bits, tile_cols);
-      pl.tile_hi[k] = pl.n_tiles;
-      pl.ops[k] = pl.filter_ops - ops0;
-      prev = c.max_size;
-    }
-
-    // the plan's tables go up in one copy: blocks, slack, omin, cmin, cmax
-    const uint64_t nL = pl.slack.size(), nA = pl.cmin.size(), nB = pl.blocks.size();
-    constexpr uint64_t kBlockWords = sizeof(RowBlock) / 4;
-    std::vector<uint32_t> packed(kBlockWords * nB + 2 * nL + 2 * nA);
-    std::memcpy(packed.data(), pl.blocks.data(), nB * sizeof(RowBlock));
-    uint32_t *tab = packed.data() + kBlockWords * nB;
-    std::memcpy(tab, pl.slack.data(), nL * 4);
-    std::memcpy(tab + nL, pl.omin.data(), nL * 4);
-    std::memcpy(tab + 2 * nL, pl.cmin.data(), nA * 4);
-    std::memcpy(tab + 2 * nL + nA, pl.cmax.data(), nA * 4);
-    uint32_t *d_packed = ar.alloc<uint32_t>(packed.size());
-    h2d(d_packed, packed.data(), packed.size(), st);
-    RowBlock *d_blocks = reinterpret_cast<RowBlock *>(d_packed);
-    uint32_t *d_tab = d_packed + kBlockWords * nB;
-    int32_t *d_slack = reinterpret_cast<int32_t *>(d_tab);
-    uint32_t *d_omin = d_tab + nL;
-    uint32_t *d_cmin = d_tab + 2 * nL;
-    uint32_t *d_cmax = d_tab + 2 * nL + nA;
-    uint32_t *d_tile_block = ar.alloc<uint32_t>(pl.n_tiles);
-    check(launch_expand_tiles(d_blocks, (uint32_t)nB, pl.n_tiles, d_tile_block, st));
-    check(hipEventRecord(t_prep.ev[1], st));
-
-    // filter / verify rounds.  A queue reservation covers one step of U
-    // columns for all of a wave's rows; the queue must hold the largest such
-    // batch, or a full step could never be written and its tile never resumed.
-    const uint64_t qcap = std::max<uint64_t>(std::max<uint64_t>(pl.max_batch, 4096),
-                                             std::min<uint64_t>(cap, pl.band_pairs + 1));
-    uint2 *queue = ar.alloc<uint2>(qcap);
-    const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
-    Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
-    uint64_t res_cap = std::max<uint64_t>(qcap, 1024);
-    unsigned long long *results = ar.alloc<unsigned long long>(res_cap);
-
-    std::deque<Timer> t_filter, t_verify;  // events must not move
-    std::vector<uint32_t> t_filter_cls;
-    uint32_t n_resume_in = 0;
-    uint64_t results_n = 0;
-    FilterConfig cfg{};
-    cfg.n_rows = (uint32_t)A.n;
-    cfg.n_cols = (uint32_t)Bc.n;
-    cfg.n_tiles = pl.n_tiles;
-    cfg.tile_cols = tile_cols;
-    cfg.self = self ? 1u : 0u;
-    cfg.n_blocks = (uint32_t)nB;
-    cfg.resume_cap = max_waves;
-    cfg.cap = qcap;
-    for (;;) {
-      if (pl.n_tiles == 0) break;
-      cfg.n_resume_in = n_resume_in;
-      // one launch per width class; after an overflow the later launches of
-      // the round leave at once and resume in the next round
-      for (uint32_t k = 0; k < pl.n_classes; ++k) {
-        if (pl.tile_hi[k] == pl.tile_lo[k]) continue;
-        cfg.tile_lo = pl.tile_lo[k];
-        cfg.tile_hi = pl.tile_hi[k];
-        cfg.cls = k;
-        const uint32_t slot = wd.slot_of(pl.words[k]);
-        FilterArgs fa{A.bm + wd.off[slot], Bc.bm + wd_b.off[slot], A.sizes, Bc.sizes,
-                      Bc.sstart, d_slack, d_cmin, d_cmax, d_blocks, d_tile_block, queue, ctr,
-                      res_a, res_b, cfg};
-        t_filter.emplace_back();
-        t_filter_cls.push_back(k);
-        check(hipEventRecord(t_filter.back().ev[0], st));
-        check(launch_filter(pl.words[k], fa, st));
-        check(hipEventRecord(t_filter.back().ev[1], st));
-      }
-      t_verify.emplace_back();
-      check(hipEventRecord(t_verify.back().ev[0], st));
-      check(launch_verify(queue, qcap, R->offsets, R->tokens, A.perm,
-                          self ? R->offsets : S->offsets, self ? R->tokens : S->tokens, Bc.perm,
-                          d_omin, (uint32_t)A.n, (uint32_t)Bc.n, self ? 1u : 0u,
-                          survivors_only ? 1u : 0u, results, res_cap, ctr, st));
-      check(hipEventRecord(t_verify.back().ev[1], st));
-      d2h(&ctr_h, ctr, 1, st);
-      sync(st);
-      if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
-      if (ctr_h.error & kErrPlan) throw Fail{SSJ_E_DEVICE};
-      results_n = ctr_h.results;
-      if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
-      if (!ctr_h.overflow) break;
-      // drain done; make room for another full queue of results, then resume
-      if (results_n + qcap > res_cap) {
-        uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
-        unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
-        check(launch_copy_u64(results, results_n, nr, st));
-        results = nr;
-        res_cap = ncap;
-      }
-      n_resume_in = ctr_h.n_resume;
-      std::swap(res_a, res_b);
-      check(launch_reset_round(ctr, st));
-    }
-    if (pl.n_tiles == 0) {
-      // nothing to filter; still report unsorted input
-      d2h(&ctr_h, ctr, 1, st);
-      sync(st);
-      if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
-    }
-
-    // emit: sort keys (i << 32 | j) by j's digits then i's, copy out
-    check(hipEventRecord(t_emit.ev[0], st));
-    ssj_pair *host = nullptr;
-    if (results_n) {
-      unsigned long long *tmp = ar.alloc<unsigned long long>(results_n);
-      uint32_t *scr = ar.alloc<uint32_t>(radix_scratch_words(results_n));
-      int shifts[8], ns = 0;
-      const uint64_t ni = self ? A.n : A.n, nj = self ? A.n : Bc.n;
-      const int bi = bits_for(ni ? ni - 1 : 0), bj = bits_for(nj ? nj - 1 : 0);
-      for (int b = 0; b < bj; b += 8) shifts[ns++] = b;
-      for (int b = 0; b < bi; b += 8) shifts[ns++] = 32 + b;
-      unsigned long long *sorted = results;
-      check(radix_sort_u64(results, tmp, results_n, shifts, ns, scr, st, &sorted));
-      ssj_pair *dpairs = ar.alloc<ssj_pair>(results_n);
-      check(launch_keys_to_pairs(sorted, results_n, dpairs, st));
-      host = static_cast<ssj_pair *>(std::malloc(results_n * sizeof(ssj_pair)));
-      if (!host) throw Fail{SSJ_E_NOMEM};
-      hipError_t e = hipMemcpyAsync(host, dpairs, results_n * sizeof(ssj_pair),
-                                    hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) {
-        std::free(host);
-        check(e);
-      }
-    }
-    check(hipEventRecord(t_emit.ev[1], st));
+    Space A, B;
+    space_begin(A, &R, 1, ar, st);
+    if (!self) space_begin(B, &S, 1, ar, st);
     sync(st);
-    out->pairs = host;
-    out->count = results_n;
-    if (stats) {
-      stats->band_pairs = pl.band_pairs;
-      stats->survivors = ctr_h.survivors;
-      stats->results = results_n;
-      stats->filter_launches = (uint32_t)t_filter.size();
-      stats->b_bits = automatic ? 0 : b_bits;
-      stats->filter_ops = pl.filter_ops;
-      stats->n_classes = (uint32_t)std::min<size_t>(classes.size(), 4);
-      prev = 0;
-      for (uint32_t k = 0; k < stats->n_classes; ++k) {
-        stats->class_bits[k] = automatic ? 64 * classes[k].words : b_bits;
-        stats->class_max_size[k] = classes[k].max_size;
-      }
-      stats->ms_prepare = t_prep.ms();
-      for (size_t k = 0; k < t_filter.size(); ++k) {
-        const float ms = t_filter[k].ms();
-        stats->ms_filter += ms;
-        stats->class_ms[t_filter_cls[k]] += ms;
-      }
-      for (uint32_t k = 0; k < stats->n_classes; ++k) stats->class_ops[k] = pl.ops[k];
-      for (auto &t : t_verify) stats->ms_verify += t.ms();
-      stats->ms_emit = t_emit.ms();
+    space_sort(A, r_bm == nullptr, ar, ar, st);
+    if (!self) space_sort(B, s_bm == nullptr, ar, ar, st);
+    sync(st);
+    space_finish(A);
+    if (!self) space_finish(B);
+    Space &C = self ? A : B;
+    if (r_bm) {
+      const uint32_t w = filter_padded_words(b_bits / 64);
+      if (!w) return SSJ_E_UNSUPPORTED;
+      space_caller_bitmaps(A, r_bm, w, b_bits, ar, ctr, st);
+      if (!self) space_caller_bitmaps(B, s_bm, w, b_bits, ar, ctr, st);
     }
+    std::vector<TaskIn> tasks{{0, 0, sim, p, q, self}};
+    run_join(A, C, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
-    std::free(out->pairs);
-    out->pairs = nullptr;
-    out->count = 0;
+    std::free(jo.pairs);
     (void)hipGetLastError();
     return f.code;
   } catch (const std::bad_alloc &) {
+    std::free(jo.pairs);
     return SSJ_E_NOMEM;
   }
-  if (stats) {
-    stats->ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
-                                                               t_start)
-                          .count();
+  out->pairs = jo.pairs;
+  out->count = jo.count;
+  if (stats) stats->ms_total = ms_since(t_start);
+  return SSJ_OK;
+}
+
+}  // namespace
+}  // namespace ssj
+
+// A resident collection for repeated R-S queries: a copy of the caller's CSR
+// in the index's own device memory, prepared (sizes, size order, group
+// starts) and with its bitmaps built once.
+struct ssj_index {
+  ssj::Arena ar;
+  ssj::Space S;
+  ssj_sets sets{};
+  uint32_t b_bits = 0;
+  int device = 0;
+  explicit ssj_index(hipStream_t st) : ar(st, true) {}
+};
+
+namespace ssj {
+namespace {
+
+// Several tasks whose row sides are `rows` (one task per side) against the
+// prepared space C (or against themselves when self).
+int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32_t *q,
+               bool self, ssj_index *idx, uint32_t b_bits, int sim, const ssj_options *opts,
+               ssj_pairs *out, uint64_t *starts, ssj_stats *stats, void *hip_stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!out) return SSJ_E_INVALID;
+  clear_out(out, stats);
+  if (n && (!rows || !p || !q)) return SSJ_E_INVALID;
+  JoinOut jo;
+  try {
+    const JoinConfig jc0 = config_of(b_bits, opts);
+    JoinConfig jc = jc0;
+    std::vector<TaskIn> tasks(n);
+    std::vector<const ssj_sets *> sides(n);
+    for (uint32_t k = 0; k < n; ++k) {
+      uint32_t pk = p[k], qk = q[k];
+      check_threshold(sim, pk, qk);
+      tasks[k] = {k, self ? k : 0u, sim, pk, qk, self};
+      sides[k] = rows + k;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (idx) {
+      int dev = 0;
+      check(hipGetDevice(&dev));
+      if (dev != idx->device) return SSJ_E_INVALID;
+      jc.b_bits = idx->b_bits;
+      jc.cols_resident = true;
+    }
+    Arena ar(st);
+    Timer t_prep;
+    check(hipEventRecord(t_prep.ev[0], st));
+    JoinCounters *ctr = ar.alloc<JoinCounters>(1);
+    check(launch_reset_all(ctr, st));
+    Space A;
+    space_begin(A, sides.data(), n, ar, st);
+    sync(st);
+    space_sort(A, true, ar, ar, st);
+    sync(st);
+    space_finish(A);
+    run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
+  } catch (const Fail &f) {
+    std::free(jo.pairs);
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    std::free(jo.pairs);
+    return SSJ_E_NOMEM;
   }
+  out->pairs = jo.pairs;
+  out->count = jo.count;
+  if (starts) {
+    if (jo.task_start.size() == (size_t)n + 1) std::memcpy(starts, jo.task_start.data(), (n + 1) * 8);
+    else std::memset(starts, 0, ((size_t)n + 1) * 8);
+  }
+  if (stats) stats->ms_total = ms_since(t_start);
   return SSJ_OK;
 }
 
@@ -713,20 +1049,17 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
     if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Arena ar(st);
-    JoinCounters *ctr = ar.alloc<JoinCounters>(1);
-    JoinCounters ctr_h;
-    check(launch_reset_all(ctr, st));
-    unsigned long long *keys = ar.alloc<unsigned long long>(s->n_sets);
-    check(launch_set_sizes(s->offsets, s->n_sets, s->n_tokens, keys, ctr, st));
-    d2h(&ctr_h, ctr, 1, st);
+    Space A;
+    space_begin(A, &s, 1, ar, st);
     sync(st);
-    if (ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
-    if (s->n_sets == 0) return s->n_tokens ? SSJ_E_INVALID : SSJ_OK;
-    check(launch_build_bitmaps(s->offsets, s->tokens, nullptr, nullptr, s->n_sets, b_bits, method,
-                               b_bits / 64, bitmaps_dev, ctr, st));
-    d2h(&ctr_h, ctr, 1, st);
+    if (A.ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
+    if (A.n == 0) return SSJ_OK;
+    // caller order: no permutation
+    check(launch_build_bitmaps(A.d_sides, 1, A.seg_blocks, A.n, nullptr, nullptr, nullptr,
+                               b_bits, method, b_bits / 64, bitmaps_dev, A.ctr, st));
+    d2h(&A.ctr_h, A.ctr, 1, st);
     sync(st);
-    if (ctr_h.error & kErrUnsorted) return SSJ_E_UNSORTED;
+    if (A.ctr_h.error & kErrUnsorted) return SSJ_E_UNSORTED;
   } catch (const Fail &f) {
     (void)hipGetLastError();
     return f.code;
@@ -739,17 +1072,100 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *
 int ssj_self_join(const ssj_sets *s, const uint64_t *bitmaps_dev, uint32_t b_bits, int sim,
                   uint32_t p, uint32_t q, const ssj_options *opts, ssj_pairs *out,
                   ssj_stats *stats, void *hip_stream) {
-  return ssj::join(s, bitmaps_dev, s, bitmaps_dev, true, b_bits, sim, p, q, opts, out, stats,
-                   hip_stream);
+  return ssj::join_one(s, bitmaps_dev, s, bitmaps_dev, true, b_bits, sim, p, q, opts, out, stats,
+                       hip_stream);
 }
 
 int ssj_rs_join(const ssj_sets *r, const uint64_t *r_bitmaps_dev, const ssj_sets *s,
                 const uint64_t *s_bitmaps_dev, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
                 const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
-  if ((r_bitmaps_dev == nullptr) != (s_bitmaps_dev == nullptr)) return SSJ_E_INVALID;
-  return ssj::join(r, r_bitmaps_dev, s, s_bitmaps_dev, false, b_bits, sim, p, q, opts, out, stats,
-                   hip_stream);
+  if ((r_bitmaps_dev == nullptr) != (s_bitmaps_dev == nullptr)) {
+    if (out) {
+      out->pairs = nullptr;
+      out->count = 0;
+    }
+    return SSJ_E_INVALID;
+  }
+  return ssj::join_one(r, r_bitmaps_dev, s, s_bitmaps_dev, false, b_bits, sim, p, q, opts, out,
+                       stats, hip_stream);
 }
+
+int ssj_self_join_batch(const ssj_sets *sets, uint32_t n_instances, const uint32_t *p,
+                        const uint32_t *q, uint32_t b_bits, int sim, const ssj_options *opts,
+                        ssj_pairs *out, uint64_t *starts, ssj_stats *stats, void *hip_stream) {
+  return ssj::join_tasks(sets, n_instances, p, q, true, nullptr, b_bits, sim, opts, out, starts,
+                         stats, hip_stream);
+}
+
+int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *hip_stream) {
+  using namespace ssj;
+  if (!out) return SSJ_E_INVALID;
+  *out = nullptr;
+  ssj_index *idx = nullptr;
+  try {
+    validate_sets(s);
+    if (b_bits != 0 && (b_bits < 64 || b_bits > 4096 || b_bits % 64)) return SSJ_E_INVALID;
+    const uint32_t wfix = b_bits ? filter_padded_words(b_bits / 64) : 0;
+    if (b_bits && !wfix) return SSJ_E_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    idx = new ssj_index(st);
+    check(hipGetDevice(&idx->device));
+    idx->b_bits = b_bits;
+    // the index's own copy of the collection
+    uint64_t *offs = idx->ar.alloc<uint64_t>(s->n_sets + 1);
+    uint32_t *toks = idx->ar.alloc<uint32_t>(s->n_tokens);
+    if (s->n_sets)
+      check(hipMemcpyAsync(offs, s->offsets, (s->n_sets + 1) * 8, hipMemcpyDeviceToDevice, st));
+    if (s->n_tokens)
+      check(hipMemcpyAsync(toks, s->tokens, s->n_tokens * 4, hipMemcpyDeviceToDevice, st));
+    idx->sets = ssj_sets{s->n_sets ? offs : nullptr, s->n_tokens ? toks : nullptr, s->n_sets,
+                         s->n_tokens};
+    const ssj_sets *side = &idx->sets;
+    {
+      Arena tmp(st);
+      space_begin(idx->S, &side, 1, idx->ar, st);
+      sync(st);
+      space_sort(idx->S, true, idx->ar, tmp, st);
+      sync(st);
+      space_finish(idx->S);
+      JoinCounters *ctr = idx->S.ctr;
+      check(launch_reset_all(ctr, st));
+      if (b_bits) {
+        space_bitmaps(idx->S, wfix, b_bits, idx->ar, ctr, st);
+      } else {
+        for (uint32_t w : kAutoWords) space_bitmaps(idx->S, w, 64 * w, idx->ar, ctr, st);
+      }
+      d2h(&idx->S.ctr_h, ctr, 1, st);
+      sync(st);
+      if (idx->S.ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+    }
+  } catch (const Fail &f) {
+    (void)hipGetLastError();
+    delete idx;
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    delete idx;
+    return SSJ_E_NOMEM;
+  }
+  *out = idx;
+  return SSJ_OK;
+}
+
+int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
+                    const uint32_t *p, const uint32_t *q, int sim, const ssj_options *opts,
+                    ssj_pairs *out, uint64_t *starts, ssj_stats *stats, void *hip_stream) {
+  if (!idx) {
+    if (out) {
+      out->pairs = nullptr;
+      out->count = 0;
+    }
+    return SSJ_E_INVALID;
+  }
+  return ssj::join_tasks(batches, n_batches, p, q, false, idx, idx->b_bits, sim, opts, out,
+                         starts, stats, hip_stream);
+}
+
+void ssj_index_destroy(ssj_index *idx) { delete idx; }
 
 void ssj_free_pairs(ssj_pairs *out) {
   if (!out) return;

@@ -18,6 +18,11 @@ constexpr uint32_t kMaxWords = 64;
 // Threads per workgroup for every kernel of the library (4 wave64s).
 constexpr int kBlock = 256;
 
+// Partitions of a tile range (one per XCD of the MI355X).
+constexpr uint32_t kParts = 8;
+// Width classes of one join (one filter launch each).
+constexpr uint32_t kMaxClasses = 4;
+
 // Counters of one filter/verify round, in device memory.
 struct JoinCounters {
   unsigned long long queue_count;   // slots reserved in the survivor queue
@@ -30,22 +35,69 @@ struct JoinCounters {
   // Tile cursors: each width class's tile range is cut into kParts
   // contiguous partitions, one per XCD; each cursor counts the tiles handed
   // out from its partition.  Each sits in its own 128-byte line.
-  alignas(128) uint32_t tile_next[4][8][32];
+  alignas(128) uint32_t tile_next[kMaxClasses][kParts][32];
 };
-
-// Partitions of a tile range (one per XCD of the MI355X).
-constexpr uint32_t kParts = 8;
-// Width classes of one join (one filter launch each).
-constexpr uint32_t kMaxClasses = 4;
 
 constexpr uint32_t kErrOffsets = 1u;   // malformed offsets
 constexpr uint32_t kErrUnsorted = 2u;  // a set is not strictly increasing
 constexpr uint32_t kErrTooBig = 4u;    // a set has 2^32 or more tokens
-constexpr uint32_t kErrPlan = 8u;      // a row block with no filter path (internal error)
+
+// One collection of a space (device copy).  A space lays its sides out one
+// after the other: the side owns global indices [base, base + n).
+struct SideDesc {
+  const uint64_t *offsets;  // caller CSR
+  const uint32_t *tokens;
+  uint64_t n_tokens;
+  uint64_t base;
+  uint32_t n;
+  uint32_t blk0;            // first workgroup of the side in the bitmap build
+};
+
+// One join task: the rows of one side of the row space against the columns
+// of one side of the column space, with its own similarity function and
+// threshold p/q.  Its tables sit in one uint32 array at the given offsets:
+// slack[L] and omin[L] for L in [0, a_max + c_max] (functions whose least
+// overlap depends on |r| + |s| only; Cosine computes it per size pair),
+// cmin[a] and cmax[a] for a in [0, a_max].
+struct TaskDesc {
+  uint32_t slack_off;
+  uint32_t omin_off;
+  uint32_t cmin_off;
+  uint32_t cmax_off;
+  uint32_t row_side;
+  uint32_t col_side;
+  uint32_t col_base;        // global index of the column side's first set
+  uint32_t self;            // 1: rows and columns are one side (j < i only)
+  uint64_t col_sstart_off;  // the column side's group-start table
+  uint32_t sim;             // ssj_sim
+  uint32_t p, q;
+  uint32_t pad;
+};
+
+// Least overlap o with Cosine o / sqrt(a c) >= p / q (Table 1), exactly:
+// the smallest o with q^2 o^2 >= p^2 a c, in 128-bit integers.  A double
+// estimate is corrected by at most a few steps either way.
+__host__ __device__ inline uint32_t cosine_omin(uint32_t a, uint32_t c, uint32_t p, uint32_t q) {
+  const unsigned __int128 rhs = (unsigned __int128)((uint64_t)p * p) * ((uint64_t)a * c);
+  auto reaches = [&](uint64_t o) {
+    const uint64_t x = (uint64_t)q * o;
+    return (unsigned __int128)x * x >= rhs;
+  };
+  const double est = (double)p / (double)q * sqrt((double)a * (double)c);
+  uint64_t o = est > 0.0 ? (uint64_t)est : 0u;
+  while (o > 0 && reaches(o - 1)) --o;
+  while (!reaches(o)) ++o;
+  return (uint32_t)o;
+}
+
+// slack = |r| + |s| - 2 omin of a Cosine task (negative: never similar)
+__host__ __device__ inline int32_t cosine_slack(uint32_t a, uint32_t c, uint32_t p, uint32_t q) {
+  return (int32_t)((int64_t)a + c - 2 * (int64_t)cosine_omin(a, c, p, q));
+}
 
 // One row block of the filter's tile plan: up to 64*R consecutive rows
-// [row0, row_end) of the size-ordered row collection, all of one bitmap
-// width (`words` 64-bit words), and the column range they are compared with.
+// [row0, row_end) of one row side, all of one bitmap width, and the column
+// range (global column indices) they are compared with.
 // Self-join: columns [col_begin, row0) in interior tiles of tile_cols
 // columns, then one diagonal tile [row0, col_end) where only j < i counts.
 // R-S join: columns [col_begin, col_end) in tiles of tile_cols columns.
@@ -55,8 +107,9 @@ struct RowBlock {
   uint32_t col_begin;
   uint32_t col_end;
   uint32_t tile_begin;
-  uint32_t words;
-  uint32_t pad[2];
+  uint32_t task;
+  uint32_t self;
+  uint32_t pad;
 };
 
 // A tile to resume after a queue drain: tile index, first column, and the
@@ -71,28 +124,56 @@ struct Resume {
 
 // Filter launch arguments that are not hot pointers.
 struct FilterConfig {
-  uint32_t n_rows;        // rows (size order), all sets
-  uint32_t n_cols;        // columns (size order), all sets
+  uint32_t n_rows;        // rows in the row space
+  uint32_t n_cols;        // columns in the column space
   uint32_t n_tiles;
   uint32_t tile_cols;
-  uint32_t self;          // 1: self-join (triangle j < i in diagonal tiles)
   uint32_t n_resume_in;
   uint32_t n_blocks;
   uint32_t resume_cap;    // entries of the resume buffers
+  uint32_t cls;           // width class (selects the tile cursors)
   unsigned long long cap; // survivor queue capacity (entries)
   uint32_t tile_lo;       // this launch's tile range [tile_lo, tile_hi)
   uint32_t tile_hi;
-  uint32_t cls;           // width class (selects the tile cursors)
-  uint32_t pad;
 };
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 
-// sizes[k] = offsets[k+1] - offsets[k]; validates offsets; keys[k] =
-// (size << 32) | k for the size sort; tracks the largest size.
-hipError_t launch_set_sizes(const uint64_t *offsets, uint64_t n, uint64_t n_tokens,
-                            unsigned long long *keys, JoinCounters *ctr, hipStream_t st);
+// Side of global index g: the last side whose base is <= g (an empty side
+// shares its base with the next side and comes before it).
+__device__ __forceinline__ uint32_t side_of_index(const SideDesc *__restrict__ sides,
+                                                  uint32_t n_sides, uint64_t g) {
+  uint32_t lo = 0, hi = n_sides;  // sides[lo].base <= g < sides[hi].base
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sides[mid].base <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// sizes[g], side_of[g] of every set of every side; offsets validated;
+// largest size in ctr->max_size.
+hipError_t launch_set_sizes(const SideDesc *sides, uint32_t n_sides, uint64_t n_total,
+                            uint32_t *sizes, uint32_t *side_of, JoinCounters *ctr,
+                            hipStream_t st);
+// keys (side, size, caller index) for the size sort
+hipError_t launch_make_keys(const SideDesc *sides, const uint32_t *sizes, const uint32_t *side_of,
+                            uint64_t n_total, int size_bits, unsigned long long *keys,
+                            hipStream_t st);
+// sorted keys -> sizes and perm (size order -> caller index within the side)
+hipError_t launch_unpack_keys(const unsigned long long *keys, uint64_t n, int size_bits,
+                              uint32_t *sizes, uint32_t *perm, hipStream_t st);
+// per side s: sstart[s * stride + v] = first position of the side (from its
+// base) with size >= v, v in [0, max_size + 1]
+hipError_t launch_group_starts(const SideDesc *sides, const uint32_t *sizes,
+                               const uint32_t *side_of, uint64_t n_total, uint32_t max_size,
+                               uint32_t stride, uint32_t n_sides, uint32_t *sstart,
+                               hipStream_t st);
+// rank[base_s + perm[g]] = g
+hipError_t launch_invert_perm(const SideDesc *sides, const uint32_t *perm,
+                              const uint32_t *side_of, uint64_t n_total, uint32_t *rank,
+                              hipStream_t st);
 
 // Stable LSD radix sort of 64-bit keys on the digits given by `shifts`
 // (8 bits each, least significant first).  Result in *keys (ping-pong with
@@ -102,32 +183,24 @@ hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uin
                           const int *shifts, int n_shifts, uint32_t *scratch, hipStream_t st,
                           unsigned long long **result);
 
-// sorted keys -> sizes (size order) and perm (size order -> caller index)
-hipError_t launch_unpack_keys(const unsigned long long *keys, uint64_t n, uint32_t *sizes,
-                              uint32_t *perm, hipStream_t st);
-
-// sstart[s] = first size-order position whose size is >= s, s in [0, max+1]
-hipError_t launch_group_starts(const uint32_t *sizes, uint64_t n, uint32_t max_size,
-                               uint32_t *sstart, hipStream_t st);
-
-// Bitmaps (Alg. 3/4/5, h(t) = t mod b).  Output row x (x < n) is input set
-// perm ? perm[x] : x, written with `out_words` words (>= b/64; the extra
-// words are zero); rank is the inverse of perm (both or neither given).
-// Also checks that every set is strictly increasing.
-hipError_t launch_build_bitmaps(const uint64_t *offsets, const uint32_t *tokens,
-                                const uint32_t *perm, const uint32_t *rank, uint64_t n,
-                                uint32_t b_bits, int method,
+// Bitmaps (Alg. 3/4/5, h(t) = t mod b) of every set of every side, `out_words`
+// 64-bit words each (>= b/64; extra words zero).  Without perm/rank the
+// output is in caller order (row base_s + k for caller set k); with them, in
+// size order (row g for the set perm[g] of side side_of[g]).  The strict
+// token order of every set is checked on the way.
+hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_t seg_blocks,
+                                uint64_t n_total, const uint32_t *perm, const uint32_t *rank,
+                                const uint32_t *side_of, uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
                                 hipStream_t st);
+// workgroups the segmented build uses for a side of n sets
+uint32_t bitmap_seg_blocks(uint64_t n);
 
-// rank[perm[x]] = x
-hipError_t launch_invert_perm(const uint32_t *perm, uint64_t n, uint32_t *rank, hipStream_t st);
-
-// Token-order check only (when the caller brings bitmaps).
+// Token-order check only (when the caller brings bitmaps); one side.
 hipError_t launch_check_sorted(const uint64_t *offsets, const uint32_t *tokens, uint64_t n,
                                JoinCounters *ctr, hipStream_t st);
 
-// out[x] = in[perm[x]] with `in_words` words widened to `out_words`.
+// out[x] = in[perm[x]] with `in_words` words widened to `out_words` (one side).
 hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint64_t n,
                                  uint32_t in_words, uint32_t out_words, uint64_t *out,
                                  hipStream_t st);
@@ -152,10 +225,9 @@ struct FilterArgs {
   const uint64_t *bm_cols;
   const uint32_t *size_rows;
   const uint32_t *size_cols;
-  const uint32_t *sstart_cols;
-  const int32_t *slack;
-  const uint32_t *cmin;
-  const uint32_t *cmax;
+  const uint32_t *sstart_cols;  // group-start tables of the column space
+  const uint32_t *tables;       // slack / omin / cmin / cmax of every task
+  const TaskDesc *tasks;
   const RowBlock *blocks;
   const uint32_t *tile_block;
   uint2 *queue;
@@ -165,27 +237,40 @@ struct FilterArgs {
   FilterConfig cfg;
 };
 
-// One launch for the width padded_words (from filter_padded_words).
-hipError_t launch_filter(uint32_t padded_words, const FilterArgs &args, hipStream_t st);
+// One launch for the width padded_words (from filter_padded_words); cosine:
+// some task of the launch uses Cosine (a kernel variant that computes its
+// thresholds per size pair).
+hipError_t launch_filter(uint32_t padded_words, bool cosine, const FilterArgs &args,
+                         hipStream_t st);
+
+// Where verification finds a task's sets and threshold.
+struct VerifySpace {
+  const SideDesc *sides;
+  const uint32_t *side_of;
+  const uint32_t *perm;
+  uint32_t n;              // sets in the space
+};
 
 // Verification of the queued survivors (sorted merge, Table 1 predicate)
-// into 64-bit result keys (caller indices; self-join keys are (min, max)).
-hipError_t launch_verify(const uint2 *queue, unsigned long long cap, const uint64_t *off_rows,
-                         const uint32_t *tok_rows, const uint32_t *perm_rows,
-                         const uint64_t *off_cols, const uint32_t *tok_cols,
-                         const uint32_t *perm_cols, const uint32_t *omin, uint32_t n_rows,
-                         uint32_t n_cols, uint32_t self,
-                         uint32_t survivors_only, unsigned long long *results,
-                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st);
+// into 64-bit result keys (task << (ib + jb)) | (i << jb) | j of caller
+// indices (self-join pairs as (min, max)).  side_task[s]: the task of row
+// side s.
+hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
+                         VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
+                         const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
+                         unsigned long long *results, unsigned long long results_cap,
+                         JoinCounters *ctr, hipStream_t st);
 
-// reset the per-round counters of the queue (not the tile cursor)
+// Sorted result keys -> ssj_pair {i, j}; task_start[k] = first result of
+// task k (k in [0, n_tasks]).
+hipError_t launch_split_results(const unsigned long long *keys, uint64_t n, int ib, int jb,
+                                uint32_t n_tasks, ssj_pair *out, uint64_t *task_start,
+                                hipStream_t st);
+
+// reset the per-round counters of the queue (not the tile cursors)
 hipError_t launch_reset_round(JoinCounters *ctr, hipStream_t st);
 // zero a whole JoinCounters
 hipError_t launch_reset_all(JoinCounters *ctr, hipStream_t st);
-
-// keys (i << 32 | j) -> ssj_pair {i, j}
-hipError_t launch_keys_to_pairs(const unsigned long long *keys, uint64_t n, ssj_pair *out,
-                                hipStream_t st);
 
 // copy n 64-bit words
 hipError_t launch_copy_u64(const unsigned long long *in, uint64_t n, unsigned long long *out,

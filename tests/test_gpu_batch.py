@@ -1,0 +1,147 @@
+"""GPU parity of the batched form (many self-joins in one call) and the
+served form (R-S queries against a resident index), through the C ABI,
+against the CPU oracle instance by instance.  Bit-exact throughout."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1711_07295_amd as ssj
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(c):
+    return ssj.to_device(c.offsets, c.tokens)
+
+
+def _col(seed, n, universe=400, hi=60, median=10.0, planted=0.15, lo=1):
+    return gen.generate(n_sets=n, universe=universe, zipf_s=1.0, size_dist=gen.SIZE_LOGNORMAL,
+                        size_a=median, size_b=0.8, size_lo=lo, size_hi=hi,
+                        planted_frac=planted, seed=seed)
+
+
+def _mixed_instances():
+    """Uneven instances: empty, tiny, ragged, wide sets, several thresholds."""
+    cols = [gen.from_lists([]), gen.from_lists([[3, 4]]), gen.from_lists([[], [], []]),
+            gen.from_lists([[1, 2, 3], [1, 2, 3], [2, 3, 4], []])]
+    cols += [_col(500 + k, n) for k, n in enumerate((50, 300, 1500, 2500))]
+    cols += [_col(600, 1200, universe=3000, hi=700, median=60.0, planted=0.3)]
+    pq = [(1, 2), (4, 5), (7, 10), (1, 1), (1, 2), (7, 10), (4, 5), (9, 10), (3, 5)]
+    return cols, pq
+
+
+@pytest.mark.parametrize("b", [0, 64, 128])
+def test_batch_matches_oracle_per_instance(b):
+    cols, pq = _mixed_instances()
+    got, st = ssj.ssj_self_join_batch([_dev(c) for c in cols], [p for p, _ in pq],
+                                      [q for _, q in pq], b_bits=b)
+    assert len(got) == len(cols)
+    band = 0
+    for c, (p, q), g in zip(cols, pq, got):
+        want = oracle.self_join(c.offsets, c.tokens, p, q)
+        assert np.array_equal(g, want), (c.n_sets, p, q, len(g), len(want))
+        band += oracle.band_pairs(c.sizes(), p, q)
+    assert st["band_pairs"] == band
+    assert st["results"] == sum(len(g) for g in got)
+
+
+def test_batch_equals_single_calls_and_resumes_after_overflow():
+    cols = [_col(700 + k, n, universe=300, planted=0.3) for k, n in enumerate((3000, 800, 5000))]
+    pq = [(1, 2), (1, 2), (3, 5)]
+    devs = [_dev(c) for c in cols]
+    single = [ssj.ssj_self_join(d, p, q, b_bits=0)[0] for d, (p, q) in zip(devs, pq)]
+    for cap, tc in [(0, 0), (1, 0), (7000, 64), (40_000, 5)]:
+        got, st = ssj.ssj_self_join_batch(devs, [p for p, _ in pq], [q for _, q in pq],
+                                          b_bits=0, queue_capacity=cap, tile_cols=tc)
+        for g, s in zip(got, single):
+            assert np.array_equal(g, s), (cap, tc)
+        if st["survivors"] > max(cap, 4096) and cap:
+            assert st["filter_launches"] > st["n_classes"]
+
+
+def test_batch_no_instances_and_errors():
+    got, st = ssj.ssj_self_join_batch([], [], [])
+    assert got == [] and st["results"] == 0
+    good, bad = gen.from_lists([[1, 2], [1, 2]]), gen.from_lists([[1, 2], [4, 3]])
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_self_join_batch([_dev(good), _dev(bad)], [1, 1], [2, 2])
+    assert e.value.status == ssj.SSJ_E_UNSORTED
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_self_join_batch([_dev(good), _dev(good)], [1, 3], [2, 2])
+    assert e.value.status == ssj.SSJ_E_INVALID
+
+
+def test_batched_workload_sample():
+    """48 instances of the batched workload's shape (up to 20,000 sets each):
+    every instance bit-exact against the banded oracle."""
+    inst = gen.batched_instances(48, n_max=20_000)
+    got, st = ssj.ssj_self_join_batch([_dev(c) for c, _ in inst], [t[0] for _, t in inst],
+                                      [t[1] for _, t in inst])
+    for (c, (p, q)), g in zip(inst, got):
+        want, _ = oracle.self_join_banded(c.offsets, c.tokens, p, q)
+        assert np.array_equal(g, want), (c.n_sets, p, q)
+
+
+# ------------------------------------------------------------------- served
+
+
+@pytest.mark.parametrize("b", [0, 128])
+def test_index_queries_match_oracle(b):
+    sw = gen.served_workload(12, resident_sets=6000, max_batch=400)
+    res = sw.resident
+    with ssj.Index(_dev(res), b_bits=b) as idx:
+        got, st = idx.query([_dev(x) for x in sw.batches], [t[0] for t in sw.thresholds],
+                            [t[1] for t in sw.thresholds])
+        for x, (p, q), g in zip(sw.batches, sw.thresholds, got):
+            want = oracle.rs_join(x.offsets, x.tokens, res.offsets, res.tokens, p, q)
+            assert np.array_equal(g, want), (x.n_sets, p, q)
+        # the perturbed copies find their source sets
+        assert sum(len(g) for g in got) > 0
+
+
+def test_index_batch_alone_equals_batch_in_mix():
+    sw = gen.served_workload(10, resident_sets=5000, max_batch=300, seed=gen.SEED_BASE + 40)
+    res = sw.resident
+    d = _dev(res)
+    with ssj.Index(d) as idx:
+        devs = [_dev(x) for x in sw.batches]
+        ps, qs = [t[0] for t in sw.thresholds], [t[1] for t in sw.thresholds]
+        mixed, _ = idx.query(devs, ps, qs)
+        for k in range(len(devs)):
+            alone, _ = idx.query([devs[k]], [ps[k]], [qs[k]])
+            assert np.array_equal(alone[0], mixed[k])
+            direct, _ = ssj.ssj_rs_join(devs[k], d, ps[k], qs[k], b_bits=0)
+            assert np.array_equal(direct, mixed[k])
+        # reversed order, and a small queue: same pairs per batch
+        rev, _ = idx.query(devs[::-1], ps[::-1], qs[::-1], queue_capacity=1)
+        for k in range(len(devs)):
+            assert np.array_equal(rev[len(devs) - 1 - k], mixed[k])
+
+
+def test_index_outlives_the_callers_collection_and_edge_cases():
+    res = _col(800, 3000, universe=500)
+    d = _dev(res)
+    idx = ssj.Index(d)
+    want_rows = _col(801, 200, universe=500)
+    want = oracle.rs_join(want_rows.offsets, want_rows.tokens, res.offsets, res.tokens, 1, 2)
+    del d  # the index holds its own copy
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    got, _ = idx.query([_dev(want_rows)], [1], [2])
+    assert np.array_equal(got[0], want)
+    got, _ = idx.query([], [], [])
+    assert got == []
+    got, _ = idx.query([_dev(gen.from_lists([])), _dev(gen.from_lists([[], []]))], [1, 1], [2, 2])
+    assert [len(g) for g in got] == [0, 0]
+    idx.close()
+    with pytest.raises(RuntimeError):
+        idx.query([_dev(want_rows)], [1], [2])
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.Index(_dev(gen.from_lists([[2, 1]])))
+    assert e.value.status == ssj.SSJ_E_UNSORTED
+    empty = ssj.Index(_dev(gen.from_lists([])))
+    got, _ = empty.query([_dev(want_rows)], [1], [2])
+    assert len(got[0]) == 0
+    empty.close()

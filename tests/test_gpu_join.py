@@ -152,8 +152,8 @@ def test_errors_are_reported_without_output():
             ssj.ssj_self_join(d, p, q)
         assert e.value.status == ssj.SSJ_E_INVALID
     with pytest.raises(ssj.SsjError) as e:
-        ssj.ssj_self_join(d, 1, 2, sim=ssj.SSJ_SIM_COSINE)
-    assert e.value.status == ssj.SSJ_E_UNSUPPORTED
+        ssj.ssj_self_join(d, 1, 2, sim=7)
+    assert e.value.status == ssj.SSJ_E_INVALID
     bad = gen.from_lists([[1, 2], [3, 3], [9, 4]])        # repeated and decreasing tokens
     with pytest.raises(ssj.SsjError) as e:
         ssj.ssj_self_join(_dev(bad), 1, 2)
