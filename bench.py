@@ -32,12 +32,38 @@ if ROOT not in sys.path:
 PEAK_INT_OPS = 256 * 64 * 2.4e9   # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_HBM = 8.0e12                 # bytes/s
 
+# HBM bytes per launch of the dominant filter launch (the b = 64 class of the
+# 1,000,000-set workload at 4/5), from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
+# 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it: factor 2.0; WRITE_SIZE
+# 1 GiB: factor 1.0).  Valid only for the kernel sources they were taken
+# with: any change to them makes the figure null until the counters are taken
+# again.  The summary and commands are in profiles/.
+TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None,
+           "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_filter.hip", "ssj_internal.h"):
+        with open(os.path.join(ROOT, "paper_1711_07295_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    t = TRAFFIC
+    if not t["sources_sha256"] or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(col, p, q, fraction=0.005):
+def cpu_baseline(col, p, q, sim=0, fraction=0.005):
     """The oracle (banded, plain C, all host threads) on a deterministic sample:
     every 1/fraction-th row of the size order, each against its whole band."""
     import numpy as np
@@ -47,8 +73,8 @@ def cpu_baseline(col, p, q, fraction=0.005):
     step = int(round(1 / fraction))
     rows = np.arange(step // 2, col.n_sets, step, dtype=np.uint64)
     t0 = time.perf_counter()
-    _, evaluated = oracle.self_join_banded(col.offsets, col.tokens, p, q, rows=rows, order=order,
-                                           threads=threads)
+    _, evaluated = oracle.self_join_banded(col.offsets, col.tokens, p, q, sim=sim, rows=rows,
+                                           order=order, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": evaluated / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(rows)} rows (every {step}th in size order) x their length band: "
@@ -69,6 +95,7 @@ def main():
     ap.add_argument("--workload", default="selfjoin-1m")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--q", type=int, default=5)
+    ap.add_argument("--sim", choices=("jaccard", "dice", "cosine", "overlap"), default="jaccard")
     ap.add_argument("--bits", type=int, default=0,
                     help="bitmap width; 0 = automatic width per row-size class")
     ap.add_argument("--tile-cols", type=int, default=0, help="0 = the library default")
@@ -109,8 +136,12 @@ def main():
     dev = ssj.to_device(col.offsets, col.tokens)
     torch.cuda.synchronize()
 
+    sim = {"jaccard": ssj.SSJ_SIM_JACCARD, "dice": ssj.SSJ_SIM_DICE,
+           "cosine": ssj.SSJ_SIM_COSINE, "overlap": ssj.SSJ_SIM_OVERLAP}[args.sim]
+
     def step():
-        return ssj.ssj_self_join(dev, args.p, args.q, b_bits=args.bits, tile_cols=args.tile_cols)
+        return ssj.ssj_self_join(dev, args.p, args.q, b_bits=args.bits, tile_cols=args.tile_cols,
+                                 sim=sim)
 
     for w in range(args.warmup):
         pairs, st = step()
@@ -133,23 +164,17 @@ def main():
     ms_per_step = total / args.steps * 1e3
     value = band / (total / args.steps)
     # roofline of the dominant kernel: the filter launch of the width class
-    # with the most algorithmic work.  Per band pair the filter does b/32 xor
-    # + b/32 popcount-accumulate + 1 compare (int32 lane-ops) at the width of
-    # the pair's row class; the library reports that work per class.
+    # with the most algorithmic work.  Per band pair the filter's algorithmic
+    # work is b/32 xor + b/32 popcount-accumulate + 1 compare (int32
+    # lane-ops) at the width of the pair's row class; the library reports that
+    # work per class, and times every launch with events on its stream.
     s0 = stats[0]
     ncls = s0["n_classes"]
+    roof = roofline_of(stats, args.steps)
     dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
-    dom_ms = sum(s["class_ms"][dom] for s in stats) / args.steps
-    dom_launches = sum(s["filter_launches"] for s in stats) / args.steps / ncls
-    achieved = s0["class_ops"][dom] / (dom_ms / 1e3)
-    filt_ms = sum(s["ms_filter"] for s in stats) / args.steps
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
-            "unit": "Top/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
-            "kernel": f"k_filter (b = {s0['class_bits'][dom]} class)",
-            "ops_per_launch": s0["class_ops"][dom] / dom_launches,
-            "avg_launch_ms": dom_ms / dom_launches,
-            "filter_stage": {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
-                             "frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}}
+    if (args.workload == "selfjoin-1m" and (args.p, args.q) == (4, 5) and args.bits == 0
+            and args.sim == "jaccard" and s0["class_bits"][dom] == 64):
+        roof["traffic"] = traffic_bytes()
     classes = [{"max_set_size": m, "b_bits": b, "ops": o, "ms": sum(s["class_ms"][k]
                 for s in stats) / args.steps}
                for k, (m, b, o) in enumerate(zip(s0["class_max_size"][:ncls],
@@ -161,7 +186,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
-                   "threshold": f"{args.p}/{args.q}", "similarity": "jaccard",
+                   "threshold": f"{args.p}/{args.q}", "similarity": args.sim,
                    "b_bits": args.bits if args.bits else "auto", "width_classes": classes,
                    "generator": "Bitmap-Xor",
                    "band_pairs": band, "results": stats[0]["results"],
@@ -175,7 +200,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 0.5% row sample ...")
-        line["cpu_baseline"] = cpu_baseline(col, args.p, args.q)
+        line["cpu_baseline"] = cpu_baseline(col, args.p, args.q, sim)
         log(f"cpu baseline: {line['cpu_baseline']}")
     print(json.dumps(line), flush=True)
 
@@ -240,7 +265,9 @@ def run_batch(args):
         stats.append(st)
         log(f"batched step {k}: {times[-1] * 1e3:.2f} ms  filter {st['ms_filter']:.2f}  "
             f"verify {st['ms_verify']:.2f}  prepare {st['ms_prepare']:.2f}  "
-            f"emit {st['ms_emit']:.2f}  results {st['results']}")
+            f"emit {st['ms_emit']:.2f}  survivors {st['survivors']}  results {st['results']}  "
+            f"launches {st['filter_launches']}  classes {st['class_bits'][:st['n_classes']]} "
+            f"ms {[round(x, 2) for x in st['class_ms'][:st['n_classes']]]}")
     torch.cuda.synchronize()
     seq_times = []
     for k in range(max(1, args.steps // 2)):
@@ -260,7 +287,7 @@ def run_batch(args):
         "config": {"workload": f"batched-{len(inst)}", "instances": len(inst),
                    "n_sets": n_sets, "n_tokens": n_tok,
                    "b_bits": args.bits if args.bits else "auto", "band_pairs": band,
-                   "results": stats[0]["results"]},
+                   "survivors": stats[0]["survivors"], "results": stats[0]["results"]},
         "sequential": {"ms_per_step": seq_ms, "value": band / (seq_ms / 1e3),
                        "calls": len(inst)},
         "speedup_vs_sequential": seq_ms / ms,
@@ -315,6 +342,11 @@ def run_serve(args):
                "batches_per_s": len(batches) / r.wall_s, "pairs_per_s": r.band_pairs / r.wall_s,
                "calls": r.calls, "mean_batches_per_call": float(r.batches_per_call.mean()),
                "results": r.results, "measured_span_s": span}
+        det = r.calls_detail
+        ent["call_ms"] = {k: float(np.mean([d[k] for d in det]))
+                          for k in ("wall_ms", "upload_ms", "ms_total", "ms_prepare", "ms_filter",
+                                    "ms_verify", "ms_emit")}
+        ent["mean_sets_per_call"] = float(np.mean([d["sets"] for d in det]))
         loads.append(ent)
         log(f"rho {rho}: {ent}")
     idx.close()

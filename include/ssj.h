@@ -263,6 +263,24 @@ int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
  * still be running. */
 void ssj_index_destroy(ssj_index *idx);
 
+/*
+ * ssj_cutoff -- the cutoff point omega(b, t) of Section 3.4: the largest set
+ * size n for which the expected normalized overlap bound of two sets of n
+ * random tokens, E(b, n) / n (Eq. 4 Bitmap-Set, Eq. 5 Bitmap-Xor, Eq. 6
+ * Bitmap-Next), is at most the overlap fraction two n-sets need to reach the
+ * threshold (Jaccard 2t/(1+t); Dice and Cosine t).  Alg. 7 applies the
+ * bitmap filter to sets up to this size; beyond it the filter can no longer
+ * tell most dissimilar pairs apart.  Host computation only.
+ *   b_bits       bitmap width, as ssj_build_bitmaps
+ *   method       ssj_bm_method
+ *   sim, p, q    similarity function and threshold, as ssj_self_join
+ *   out          receives omega; UINT32_MAX for SSJ_SIM_OVERLAP (an absolute
+ *                threshold: never cut off); 0 on error
+ * Errors: SSJ_E_INVALID (bad b, threshold or NULL out), SSJ_E_UNSUPPORTED
+ *         (unknown method).
+ */
+int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uint32_t *out);
+
 /* Release the pairs of a join.  NULL-safe and idempotent; zeroes *out. */
 void ssj_free_pairs(ssj_pairs *out);
 

@@ -271,3 +271,85 @@ def check_pairs(r_offsets, r_tokens, s_offsets, s_tokens, pairs, p: int, q: int,
     lib.oracle_check_pairs(ro.ctypes.data, rt.ctypes.data, so.ctypes.data, st.ctypes.data,
                            pb.ctypes.data, len(pr), sim, p, q, ok.ctypes.data)
     return ok[:len(pr)].astype(bool)
+
+
+# ---- Section 3.4: expected bound (Eqs. 4-6) and the cutoff point ------------
+# Eq. 5 is evaluated as printed, as its sum over odd k, each term in log space
+# (the binomial coefficients of 2n up to 2^20 do not fit a double).
+
+def expected_bound(method: int, b: int, n: int) -> float:
+    """E(b, n): the expected overlap bound (Eq. 2 without the floor) of two
+    sets of n random tokens each (Eqs. 4, 5, 6)."""
+    import math
+    b, n = int(b), int(n)
+    if method == BM_SET:      # Eq. 4
+        return n + math.exp(2 * n * math.log(b - 1) - (2 * n - 1) * math.log(b)) \
+            - math.exp(n * math.log(b - 1) - (n - 1) * math.log(b))
+    if method == BM_XOR:      # Eq. 5
+        from scipy.special import gammaln
+        k = np.arange(1, 2 * n + 1, 2, dtype=np.float64)
+        m = 2.0 * n
+        log_terms = (gammaln(m + 1) - gammaln(k + 1) - gammaln(m - k + 1)
+                     - k * math.log(b) + (m - k) * math.log((b - 1) / b))
+        return n - b / 2 * float(np.exp(log_terms).sum())
+    if method == BM_NEXT:     # Eq. 6
+        return min(n * n / b, float(n))
+    raise ValueError(method)
+
+
+def expected_bound_exact(method: int, b: int, n: int):
+    """E(b, n) as an exact Fraction, for the comparisons the floating value
+    cannot decide.  Eq. 5's sum over odd k of C(2n, k) (b-1)^(2n-k) is the
+    odd half of the binomial expansion of (1 + (b-1))^(2n), i.e.
+    (b^(2n) - (b-2)^(2n)) / 2 -- an identity the tests check against the
+    term-by-term sum."""
+    from fractions import Fraction
+    if method == BM_SET:
+        return Fraction(n) + Fraction((b - 1) ** (2 * n), b ** (2 * n - 1)) \
+            - Fraction((b - 1) ** n, b ** (n - 1))
+    if method == BM_XOR:
+        odd = (b ** (2 * n) - (b - 2) ** (2 * n)) // 2
+        return Fraction(n) - Fraction(b, 2) * Fraction(odd, b ** (2 * n))
+    return min(Fraction(n * n, b), Fraction(n))
+
+
+def normalized_threshold(sim: int, p: int, q: int):
+    """The overlap fraction o/n two sets of n tokens need to reach sim >= p/q
+    (the normalized scale of Fig. 5), exactly: Jaccard 2t/(1+t), Dice and
+    Cosine t."""
+    from fractions import Fraction
+    t = Fraction(p, q)
+    if sim == JACCARD:
+        return 2 * t / (1 + t)
+    if sim in (DICE, COSINE):
+        return t
+    raise ValueError("no normalized threshold for Overlap")
+
+
+def cutoff(method: int, b: int, tau, n_max: int = 1 << 20) -> int:
+    """Section 3.4: the cutoff point, the largest set size n at which the
+    expected normalized bound E(b, n)/n is still at most tau; Alg. 7 applies
+    the filter to sets up to this size.  E(b, n)/n grows with n, so the
+    largest such n is found by bisection.  0 when n = 1 already exceeds tau.
+    tau: a Fraction, or a decimal given as a string or float."""
+    from fractions import Fraction
+    tau = Fraction(str(tau)) if isinstance(tau, float) else Fraction(tau)
+
+    def ok(n):
+        v = expected_bound(method, b, n) / n
+        if abs(v - float(tau)) > 1e-9:
+            return v <= float(tau)
+        return expected_bound_exact(method, b, n) / n <= tau
+
+    if not ok(1):
+        return 0
+    lo, hi = 1, n_max          # ok(lo); the answer is below hi or is n_max
+    if ok(hi):
+        return hi
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if ok(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo

@@ -25,7 +25,8 @@ SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT = 0, 1, 2
 SSJ_FLAG_SURVIVORS_ONLY = 1
 
 EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
-           "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_free_pairs",
+           "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_cutoff",
+           "ssj_free_pairs",
            "ssj_status_string", "ssj_abi_version")
 
 
@@ -107,6 +108,8 @@ def load() -> ctypes.CDLL:
         lib.ssj_index_query.restype = c_int
         lib.ssj_index_destroy.argtypes = [vp]
         lib.ssj_index_destroy.restype = None
+        lib.ssj_cutoff.argtypes = [u32, c_int, c_int, u32, u32, u32p]
+        lib.ssj_cutoff.restype = c_int
         lib.ssj_free_pairs.argtypes = [ctypes.POINTER(ssj_pairs)]
         lib.ssj_free_pairs.restype = None
         lib.ssj_status_string.argtypes = [c_int]
@@ -308,6 +311,16 @@ class Index:
             self.close()
         except Exception:
             pass
+
+
+def ssj_cutoff(b_bits: int, p: int, q: int, method: int = SSJ_BM_XOR,
+               sim: int = SSJ_SIM_JACCARD) -> int:
+    """The cutoff point omega(b, p/q) of Section 3.4 (host computation)."""
+    out = ctypes.c_uint32()
+    st = load().ssj_cutoff(b_bits, method, sim, p, q, ctypes.byref(out))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_cutoff")
+    return int(out.value)
 
 
 def ssj_free_pairs(out: ssj_pairs) -> None:

@@ -25,6 +25,8 @@
 // survivor queue is full the wave marks its reserved slots as sentinels,
 // records (tile, column) to resume from, sets the overflow flag and stops;
 // the host verifies the queue and relaunches with the resume list.
+#include <algorithm>
+
 #include "ssj_internal.h"
 
 namespace ssj {
@@ -66,6 +68,32 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
   uint32_t r;
   asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
   return r;
+}
+
+// bias + popcount(b_r xor b_c) with bias = -(slack + 1): negative exactly
+// when the pair is kept.  The compare is folded into the popcount chain's
+// starting value, so the sign bits of many pairs can be ORed together and
+// tested once.
+template <int W, int R>
+__device__ __forceinline__ uint32_t biased_distance(const Rows<W, R> &rw, const uint32_t *cb,
+                                                    int r, uint32_t bias) {
+  uint32_t h = bcnt_acc(rw.bits[r][0] ^ cb[0], bias);
+#pragma unroll
+  for (int e = 1; e < 2 * W; ++e) h = bcnt_acc(rw.bits[r][e] ^ cb[e], h);
+  return h;
+}
+
+// Whether some (column u, row r) pair of a step is kept: the OR of the
+// biased distances has its sign bit set.
+template <int W, int R, int U>
+__device__ __forceinline__ bool step_any(const Rows<W, R> &rw, const uint32_t (&cb)[U][2 * W],
+                                         const uint32_t (&bias)[R]) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc |= biased_distance<W, R>(rw, cb[u], r, bias[r]);
+  return __ballot((int32_t)acc < 0) != 0;
 }
 
 template <int W, int R, bool DIAG>
@@ -141,44 +169,78 @@ __device__ __forceinline__ const_u32_ptr as_const(const uint64_t *p) {
   return (const_u32_ptr)(p);
 }
 
+// Bitmaps of columns [j, j + U) into SGPRs.
+template <int W, int U>
+__device__ __forceinline__ void load_cols(const uint64_t *__restrict__ bm_cols, uint32_t j,
+                                          uint32_t (&cb)[U][2 * W]) {
+  const_u32_ptr p = as_const(bm_cols + (size_t)j * W);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 2 * W; ++e) cb[u][e] = p[u * 2 * W + e];
+}
+
+// j, once every scalar load issued so far (the current step's columns)
+// has arrived: the next step's load is then issued after that wait, on
+// every path.
+__device__ __forceinline__ uint32_t after(uint32_t j) {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0); vmcnt, expcnt untouched
+  return j;
+}
+
+// One step: columns [j, j + U) against the wave's rows; the slow path
+// writes the kept pairs.  False when the queue filled.
+template <int W, int R, int U, bool DIAG>
+__device__ __forceinline__ bool step(const uint64_t *__restrict__ bm_rows,
+                                     const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
+                                     uint32_t row0, uint32_t row_end, const int32_t (&thr)[R],
+                                     const uint32_t (&bias)[R], const uint32_t (&cb)[U][2 * W],
+                                     uint32_t j, Sink &sink) {
+  bool any;
+  if (DIAG) {
+    unsigned long long m = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r) m |= __ballot(keep<W, R, DIAG>(rw, cb[u], r, thr[r], j + u));
+    any = m != 0;
+  } else {
+    any = step_any<W, R, U>(rw, cb, bias);
+  }
+  if (any) return emit<W, R, U, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink);
+  return true;
+}
+
 // Columns [j, g1) of one size group.
 template <int W, int R, int U, bool DIAG>
 __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_rows,
                                       const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
                                       uint32_t row0, uint32_t row_end, const int32_t (&thr)[R],
                                       uint32_t j, uint32_t g1, Sink &sink) {
+  uint32_t bias[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) bias[r] = (uint32_t)(-thr[r] - 1);
   // Scalar loads may return out of order, so a wave can only wait for all
-  // of them; the next step's columns are therefore requested right after the
-  // wait for the current step and arrive while the current step computes.
-  uint32_t nb[U][2 * W];
-  if (j + U <= g1) {
-    const_u32_ptr p = as_const(bm_cols + (size_t)j * W);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int e = 0; e < 2 * W; ++e) nb[u][e] = p[u * 2 * W + e];
-  }
-  for (; j + U <= g1; j += U) {
-    uint32_t cb[U][2 * W];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int e = 0; e < 2 * W; ++e) cb[u][e] = nb[u][e];
-    if (j + 2 * U <= g1) {
-      const_u32_ptr p = as_const(bm_cols + (size_t)(j + U) * W);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int e = 0; e < 2 * W; ++e) nb[u][e] = p[u * 2 * W + e];
-    }
-    unsigned long long any = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int r = 0; r < R; ++r) any |= __ballot(keep<W, R, DIAG>(rw, cb[u], r, thr[r], j + u));
-    if (any) {
-      if (!emit<W, R, U, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink)) return false;
-    }
+  // of them.  Two register buffers alternate: the wait for the current
+  // step's columns comes before the next step's load is issued (the next
+  // address is made to depend on the current columns), so the next load
+  // is in flight while the current step computes, and no registers are
+  // copied between steps.
+  uint32_t ba[U][2 * W], bb[U][2 * W];
+  if (j + U <= g1) load_cols<W, U>(bm_cols, j, ba);
+  for (;;) {
+    if (j + U > g1) break;
+    const uint32_t jb = after(j + U);
+    if (jb + U <= g1) load_cols<W, U>(bm_cols, jb, bb);
+    if (!step<W, R, U, DIAG>(bm_rows, bm_cols, rw, row0, row_end, thr, bias, ba, j, sink))
+      return false;
+    j += U;
+    if (j + U > g1) break;
+    const uint32_t ja = after(j + U);
+    if (ja + U <= g1) load_cols<W, U>(bm_cols, ja, ba);
+    if (!step<W, R, U, DIAG>(bm_rows, bm_cols, rw, row0, row_end, thr, bias, bb, j, sink))
+      return false;
+    j += U;
   }
   for (; j < g1; ++j) {
     uint32_t cb[1][2 * W];
@@ -442,7 +504,14 @@ int filter_grid_blocks() {
 
 hipError_t launch_filter(uint32_t padded_words, bool cosine, const FilterArgs &a,
                          hipStream_t st) {
-  dim3 grid(filter_grid_blocks());
+  // a persistent grid, but no more waves than the launch has tiles or resume
+  // entries to hand out (small width classes would otherwise start thousands
+  // of waves that find nothing to do); wave k takes resume entry k
+  const uint64_t need = std::max<uint64_t>(
+      std::max<uint64_t>(a.cfg.tile_hi - a.cfg.tile_lo, a.cfg.n_resume_in), 1);
+  const uint64_t waves_per_block = kBlock / 64;
+  dim3 grid((unsigned)std::min<uint64_t>((uint64_t)filter_grid_blocks(),
+                                         (need + waves_per_block - 1) / waves_per_block));
 #define X(w, r, u)                                              \
   if (padded_words == (w))                                      \
     return cosine ? launch_shape<w, r, u, true>(grid, st, a)    \

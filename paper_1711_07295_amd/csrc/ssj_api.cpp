@@ -32,6 +32,10 @@ namespace {
 
 constexpr uint64_t kDefaultQueue = 1ull << 27;   // 1 GiB of (row, column) pairs
 constexpr uint32_t kDefaultTileCols = 2048;
+// A width class with fewer than about kMinSlotTiles tiles of the default
+// width gets narrower tiles, down to kMinTileCols columns.
+constexpr uint64_t kMinSlotTiles = 16384;
+constexpr uint32_t kMinTileCols = 64;
 constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
 
 struct Fail {
@@ -454,6 +458,67 @@ std::vector<WidthClass> choose_classes(uint32_t max_rows, int sim, uint64_t p, u
   return cls;
 }
 
+// ------------------------------------------------------------ cutoff point
+// E(b, n) of Section 3.4 for two sets of n random tokens (Eqs. 4-6) in
+// closed form: Eq. 5's sum over odd k is the odd half of a binomial
+// expansion, (1 - (1 - 2/b)^(2n)) / 2, so E = n - (b/4)(1 - (1 - 2/b)^(2n)).
+// The overlap fraction o/n two n-sets need for sim >= p/q, as P/Q: Jaccard
+// 2t/(1+t) = 2p/(p+q), Dice and Cosine t = p/q.  False for Overlap, which has
+// none.
+bool normalized_threshold(int sim, uint64_t p, uint64_t q, uint64_t &P, uint64_t &Q) {
+  if (sim == SSJ_SIM_JACCARD) {
+    P = 2 * p;
+    Q = p + q;
+    return true;
+  }
+  if (sim == SSJ_SIM_DICE || sim == SSJ_SIM_COSINE) {
+    P = p;
+    Q = q;
+    return true;
+  }
+  return false;
+}
+
+// Whether E(b, n)/n <= P/Q.  The part of E/n that is rational is compared
+// in integers, so that thresholds it meets exactly are decided exactly:
+//   Xor   E/n - P/Q = [4n(Q-P) - bQ] / (4nQ) + (b/4n) r^(2n),  r = 1 - 2/b
+//   Set   E/n - P/Q = (Q-P)/Q - (b/n) (s^n - s^(2n)),           s = 1 - 1/b
+//   Next  E/n = n/b below saturation
+bool bound_within(int method, uint64_t b, uint64_t n, uint64_t P, uint64_t Q) {
+  if (P >= Q) return true;  // a normalized bound never exceeds 1
+  switch (method) {
+    case SSJ_BM_NEXT:
+      return n <= b && n * Q <= P * b;
+    case SSJ_BM_SET: {
+      const double sn = std::pow(1.0 - 1.0 / (double)b, (double)n);
+      return (double)(Q - P) / (double)Q <= (double)b / (double)n * (sn - sn * sn);
+    }
+    default: {
+      const int64_t num = (int64_t)(4 * n * (Q - P)) - (int64_t)(b * Q);
+      if (num >= 0) return false;  // the remaining term is positive
+      const double r2n = std::pow(1.0 - 2.0 / (double)b, 2.0 * (double)n);
+      return (double)b * (double)Q * r2n <= (double)(-num);
+    }
+  }
+}
+
+// The largest n with E(b, n)/n <= tau (E/n grows with n), up to 2^20; the
+// filter is applied to sets up to this size (Alg. 7).  UINT32_MAX: never
+// cut off (Overlap).
+uint32_t cutoff_point(int method, uint32_t b, int sim, uint64_t p, uint64_t q) {
+  uint64_t P = 0, Q = 1;
+  if (!normalized_threshold(sim, p, q, P, Q)) return 0xFFFFFFFFu;
+  auto ok = [&](uint64_t n) { return bound_within(method, b, n, P, Q); };
+  if (!ok(1)) return 0;
+  uint64_t lo = 1, hi = 1ull << 20;
+  if (ok(hi)) return (uint32_t)hi;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (ok(mid)) lo = mid; else hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
 // ------------------------------------------------------------------- plan
 
 // One task of a call, as planned on the host (p/q reduced).
@@ -479,6 +544,7 @@ struct Plan {
   uint32_t slot_bits[kMaxClasses] = {0, 0, 0, 0};
   uint32_t slot_max_size[kMaxClasses] = {0, 0, 0, 0};
   uint32_t tile_lo[kMaxClasses] = {0, 0, 0, 0}, tile_hi[kMaxClasses] = {0, 0, 0, 0};
+  uint32_t slot_tile_cols[kMaxClasses] = {0, 0, 0, 0};
   uint64_t ops[kMaxClasses] = {0, 0, 0, 0};
 };
 
@@ -515,10 +581,11 @@ void add_tables(Plan &pl, TaskDesc &td, uint64_t a_max, uint64_t c_max, int sim,
 
 // Row blocks and tiles of one task's length band for its rows of size in
 // (lo, hi], which use `words`-word bitmaps of nominal width `bits`; blocks
-// never straddle width classes.
+// never straddle width classes.  With count_only, only the band pairs are
+// added to band_out.
 void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint32_t task_id,
                 uint32_t lo, uint32_t hi, uint32_t words, uint32_t bits, uint32_t tile_cols,
-                uint64_t &band_out) {
+                uint64_t &band_out, bool count_only = false) {
   const TaskDesc &td = pl.tasks[task_id];
   const uint32_t *rs = R.ss(tk.row_side), *cs = C.ss(tk.col_side);
   const uint64_t a_max = R.side_max[tk.row_side], c_max = C.side_max[tk.col_side];
@@ -560,6 +627,7 @@ void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint
     }
   }
   band_out += band;
+  if (count_only) return;
   pl.band_pairs += band;
   pl.filter_ops += band * (bits / 16 + 1);
 
@@ -635,6 +703,7 @@ struct JoinOut {
 struct JoinConfig {
   uint32_t b_bits = 0;         // 0: width classes chosen per task
   uint32_t tile_cols = kDefaultTileCols;
+  bool tile_cols_fixed = false;  // the caller chose tile_cols
   uint64_t cap = kDefaultQueue;
   bool survivors_only = false;
   bool cols_resident = false;  // the column space is an index's: no bitmaps are added to it
@@ -696,8 +765,27 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       space_bitmaps(C, pl.slot_words[k], pl.slot_bits[k], ar, ctr, st);
     }
   }
-  // tiles, slot by slot, task by task
+  // tiles, slot by slot, task by task.  Unless the caller fixed the tile
+  // width, a slot with little work gets narrower tiles, so that it is cut
+  // into enough tiles to occupy every wave of the GPU.
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    uint32_t tile_cols = jc.tile_cols;
+    if (!jc.tile_cols_fixed) {
+      uint64_t slot_band = 0;
+      for (uint32_t t = 0; t < n_tasks; ++t) {
+        uint32_t prev = 0;
+        for (auto &c : classes[t]) {
+          if (c.words == pl.slot_words[k])
+            plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
+                       tile_cols, slot_band, true);
+          prev = c.max_size;
+        }
+      }
+      const uint64_t rows = filter_shape(pl.slot_words[k]).rows;
+      const uint64_t want = slot_band / (rows * kMinSlotTiles);
+      tile_cols = (uint32_t)std::max<uint64_t>(kMinTileCols, std::min<uint64_t>(tile_cols, want));
+    }
+    pl.slot_tile_cols[k] = tile_cols;
     pl.tile_lo[k] = pl.n_tiles;
     const uint64_t ops0 = pl.filter_ops;
     for (uint32_t t = 0; t < n_tasks; ++t) {
@@ -705,7 +793,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       for (auto &c : classes[t]) {
         if (c.words == pl.slot_words[k]) {
           plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
-                     jc.tile_cols, task_band[t]);
+                     tile_cols, task_band[t]);
           pl.slot_max_size[k] = std::max(pl.slot_max_size[k], c.max_size);
         }
         prev = c.max_size;
@@ -763,7 +851,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   cfg.n_rows = (uint32_t)R.n;
   cfg.n_cols = (uint32_t)C.n;
   cfg.n_tiles = pl.n_tiles;
-  cfg.tile_cols = jc.tile_cols;
+
   cfg.n_blocks = (uint32_t)nB;
   cfg.resume_cap = max_waves;
   cfg.cap = qcap;
@@ -776,6 +864,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       if (pl.tile_hi[k] == pl.tile_lo[k]) continue;
       cfg.tile_lo = pl.tile_lo[k];
       cfg.tile_hi = pl.tile_hi[k];
+      cfg.tile_cols = pl.slot_tile_cols[k];
       cfg.cls = k;
       const uint32_t w = pl.slot_words[k];
       FilterArgs fa{R.bitmaps(w), C.bitmaps(w), R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
@@ -876,7 +965,10 @@ JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
   if (b_bits != 0 && (b_bits < 64 || b_bits > 4096 || b_bits % 64)) throw Fail{SSJ_E_INVALID};
   JoinConfig jc;
   jc.b_bits = b_bits;
-  if (opts && opts->tile_cols) jc.tile_cols = opts->tile_cols;
+  if (opts && opts->tile_cols) {
+    jc.tile_cols = opts->tile_cols;
+    jc.tile_cols_fixed = true;
+  }
   if (opts && opts->queue_capacity) jc.cap = opts->queue_capacity;
   jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
   return jc;
@@ -1166,6 +1258,21 @@ int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
 }
 
 void ssj_index_destroy(ssj_index *idx) { delete idx; }
+
+int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uint32_t *out) {
+  using namespace ssj;
+  if (!out) return SSJ_E_INVALID;
+  *out = 0;
+  if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
+  if (method < SSJ_BM_XOR || method > SSJ_BM_NEXT) return SSJ_E_UNSUPPORTED;
+  try {
+    check_threshold(sim, p, q);
+  } catch (const Fail &f) {
+    return f.code;
+  }
+  *out = cutoff_point(method, b_bits, sim, p, q);
+  return SSJ_OK;
+}
 
 void ssj_free_pairs(ssj_pairs *out) {
   if (!out) return;

@@ -46,6 +46,7 @@ class ServeResult:
     band_pairs: int
     results: int
     pairs: list = field(default_factory=list)  # per batch, when kept
+    calls_detail: list = field(default_factory=list)  # per call: sizes and time split
 
 
 class ContinuousBatcher:
@@ -63,8 +64,10 @@ class ContinuousBatcher:
         off_all = np.concatenate(offs).view(np.int64)
         tok_all = (np.concatenate(toks) if sum(t.size for t in toks) else
                    np.zeros(0, dtype=np.uint32)).view(np.int32)
+        t0 = time.perf_counter()
         d_off = torch.from_numpy(off_all).to(device, non_blocking=False)
         d_tok = torch.from_numpy(tok_all).to(device, non_blocking=False)
+        self._upload_s = time.perf_counter() - t0
         views, o_at, t_at = [], 0, 0
         for o, t in zip(offs, toks):
             views.append(DeviceSets(d_off[o_at:o_at + o.size], d_tok[t_at:t_at + t.size]))
@@ -80,7 +83,7 @@ class ContinuousBatcher:
         arrivals = np.asarray(arrivals, dtype=np.float64)
         done = np.zeros(n)
         start_of = np.zeros(n)
-        per_call, band, results = [], 0, 0
+        per_call, band, results, detail = [], 0, 0, []
         kept = [None] * n if self.keep_pairs else []
         nxt = 0
         t0 = time.perf_counter()
@@ -102,6 +105,11 @@ class ContinuousBatcher:
             got, st = self._call([batches[i] for i in take], [thresholds[i] for i in take],
                                  device)
             end = time.perf_counter() - t0
+            detail.append({"batches": len(take), "sets": sum(batches[i].n_sets for i in take),
+                           "wall_ms": (end - now) * 1e3, "upload_ms": self._upload_s * 1e3,
+                           **{f: st[f] for f in ("ms_total", "ms_prepare", "ms_filter",
+                                                 "ms_verify", "ms_emit", "band_pairs",
+                                                 "survivors", "results")}})
             for i, g in zip(take, got):
                 done[i] = end
                 start_of[i] = now
@@ -114,7 +122,7 @@ class ContinuousBatcher:
         return ServeResult(latency_s=done - arrivals, wait_s=start_of - arrivals,
                            calls=len(per_call), batches_per_call=np.array(per_call),
                            wall_s=float(done.max() - arrivals.min()) if n else 0.0,
-                           band_pairs=band, results=results, pairs=kept)
+                           band_pairs=band, results=results, pairs=kept, calls_detail=detail)
 
 
 def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:

@@ -78,3 +78,37 @@ def test_from_lists_and_subset():
 def test_scaled_workloads_are_valid(name):
     c = gen.workload(name, n_sets=20_000)
     _check_csr(c)
+
+
+def test_batched_instances_are_seeded_and_shaped():
+    a = gen.batched_instances(6, n_max=3000)
+    b = gen.batched_instances(6, n_max=3000)
+    assert [c.checksum() for c, _ in a] == [c.checksum() for c, _ in b]
+    for c, t in a:
+        assert 1000 <= c.n_sets <= 3000
+        s = c.sizes()
+        assert s.min() >= 2 and s.max() <= 2000
+        assert t in gen.BATCH_THRESHOLDS
+        for k in range(0, c.n_sets, 97):
+            x = c.set(k)
+            assert np.all(np.diff(x.astype(np.int64)) > 0)
+
+
+def test_served_workload_copies_and_fresh_sets():
+    sw = gen.served_workload(8, resident_sets=3000, max_batch=200)
+    assert sw.resident.n_sets == 3000 and len(sw.batches) == 8
+    assert all(t in gen.SERVE_THRESHOLDS for t in sw.thresholds)
+    res = {tuple(sw.resident.set(k)) for k in range(sw.resident.n_sets)}
+    n_copy = n_close = 0
+    for bt, cp in zip(sw.batches, sw.copies):
+        assert bt.n_sets == len(cp)
+        for k in range(bt.n_sets):
+            x = bt.set(k)
+            assert np.all(np.diff(x.astype(np.int64)) > 0)
+            if cp[k]:
+                n_copy += 1
+                # a copy keeps about 90% of some resident set
+                xs = set(int(v) for v in x)
+                best = max(len(xs & set(r)) / len(xs) for r in res if abs(len(r) - len(xs)) <= 1)
+                n_close += best >= 0.8
+    assert n_copy > 0 and n_close == n_copy

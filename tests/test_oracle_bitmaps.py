@@ -5,7 +5,6 @@ negatives, the Fig. 4 arithmetic, and Monte Carlo means against the closed
 forms of Eqs. 4-6."""
 import json
 import os
-from math import comb
 
 import numpy as np
 import pytest
@@ -199,16 +198,15 @@ def test_survivors_equal_results_without_collisions():
 # ---- Eqs. 4-6: expected overlap bound of two random disjoint n-sets ----------
 
 def _eq4_set(b, n):
-    return n + (b - 1) ** (2 * n) / b ** (2 * n - 1) - (b - 1) ** n / b ** (n - 1)
+    return oracle.expected_bound(oracle.BM_SET, b, n)
 
 
 def _eq5_xor(b, n):
-    return n - b / 2 * sum(comb(2 * n, k) * (1 / b) ** k * ((b - 1) / b) ** (2 * n - k)
-                           for k in range(1, 2 * n + 1, 2))
+    return oracle.expected_bound(oracle.BM_XOR, b, n)
 
 
 def _eq6_next(b, n):
-    return min(n * n / b, n)
+    return oracle.expected_bound(oracle.BM_NEXT, b, n)
 
 
 def _mean_bound(method, b, n, pairs, seed):
