@@ -39,8 +39,9 @@ PEAK_HBM = 8.0e12                 # bytes/s
 # 1 GiB: factor 1.0).  Valid only for the kernel sources they were taken
 # with: any change to them makes the figure null until the counters are taken
 # again.  The summary and commands are in profiles/.
-TRAFFIC = {"sources_sha256": None, "fetch_kib": None, "write_kib": None,
-           "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"sources_sha256": "595dd85fb0d8137d32ee123cd83ecf43dfcac13b7f93946b8593d77c49fc20d8",
+           "fetch_kib": 44699.2, "write_kib": 24249.1,
+           "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
 def kernel_sources_sha256():
@@ -99,6 +100,8 @@ def main():
     ap.add_argument("--bits", type=int, default=0,
                     help="bitmap width; 0 = automatic width per row-size class")
     ap.add_argument("--tile-cols", type=int, default=0, help="0 = the library default")
+    ap.add_argument("--cutoff", action="store_true",
+                    help="rows past the cutoff point take prefix-filtered candidates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (reference for the "
@@ -136,12 +139,13 @@ def main():
     dev = ssj.to_device(col.offsets, col.tokens)
     torch.cuda.synchronize()
 
+    flags = ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0
     sim = {"jaccard": ssj.SSJ_SIM_JACCARD, "dice": ssj.SSJ_SIM_DICE,
            "cosine": ssj.SSJ_SIM_COSINE, "overlap": ssj.SSJ_SIM_OVERLAP}[args.sim]
 
     def step():
         return ssj.ssj_self_join(dev, args.p, args.q, b_bits=args.bits, tile_cols=args.tile_cols,
-                                 sim=sim)
+                                 sim=sim, flags=flags)
 
     for w in range(args.warmup):
         pairs, st = step()
@@ -187,6 +191,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
                    "threshold": f"{args.p}/{args.q}", "similarity": args.sim,
+                   "cutoff": args.cutoff,
                    "b_bits": args.bits if args.bits else "auto", "width_classes": classes,
                    "generator": "Bitmap-Xor",
                    "band_pairs": band, "results": stats[0]["results"],
@@ -241,13 +246,17 @@ def run_batch(args):
     ps, qs = [t[0] for _, t in inst], [t[1] for _, t in inst]
     torch.cuda.synchronize()
 
+    flags = ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0
+
     def batched():
-        return ssj.ssj_self_join_batch(devs, ps, qs, b_bits=args.bits, tile_cols=args.tile_cols)
+        return ssj.ssj_self_join_batch(devs, ps, qs, b_bits=args.bits, tile_cols=args.tile_cols,
+                                       flags=flags)
 
     def sequential():
         band, res = 0, 0
         for d, p, q in zip(devs, ps, qs):
-            _, st = ssj.ssj_self_join(d, p, q, b_bits=args.bits, tile_cols=args.tile_cols)
+            _, st = ssj.ssj_self_join(d, p, q, b_bits=args.bits, tile_cols=args.tile_cols,
+                                      flags=flags)
             band += st["band_pairs"]
             res += st["results"]
         return band, res
@@ -287,6 +296,7 @@ def run_batch(args):
         "config": {"workload": f"batched-{len(inst)}", "instances": len(inst),
                    "n_sets": n_sets, "n_tokens": n_tok,
                    "b_bits": args.bits if args.bits else "auto", "band_pairs": band,
+                   "cutoff": args.cutoff,
                    "survivors": stats[0]["survivors"], "results": stats[0]["results"]},
         "sequential": {"ms_per_step": seq_ms, "value": band / (seq_ms / 1e3),
                        "calls": len(inst)},
@@ -318,7 +328,7 @@ def run_serve(args):
     idx = ssj.Index(ssj.to_device(sw.resident.offsets, sw.resident.tokens), b_bits=args.bits)
     torch.cuda.synchronize()
     log(f"index built in {time.perf_counter() - t1:.2f} s")
-    srv = ContinuousBatcher(idx)
+    srv = ContinuousBatcher(idx, flags=ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0)
     batches, thr = sw.batches, sw.thresholds
     # plain service rate: one batch per call, back to back
     n_plain = min(300, len(batches))
@@ -359,7 +369,7 @@ def run_serve(args):
         "data": "synthetic",
         "config": {"workload": f"served-{sw.resident.n_sets}", "resident_sets": sw.resident.n_sets,
                    "batches": len(batches),
-                   "b_bits": args.bits if args.bits else "auto",
+                   "b_bits": args.bits if args.bits else "auto", "cutoff": args.cutoff,
                    "plain_service_rate": mu},
         "latency": {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rho": 0.95},
         "loads": loads,

@@ -133,6 +133,13 @@ typedef struct {
  * survivor set (caller indices), not the join. */
 #define SSJ_FLAG_SURVIVORS_ONLY 1u
 
+/* Apply the bitmap filter only to rows up to the cutoff point (Section 3.4,
+ * as Alg. 7 does; see ssj_cutoff) of their widest width; rows of larger
+ * sets take their candidates from an index of set prefixes (the prefix
+ * filter) instead.  Changes the work, never the result.  With
+ * SSJ_FLAG_SURVIVORS_ONLY those rows report their prefix candidates. */
+#define SSJ_FLAG_CUTOFF 2u
+
 /*
  * ssj_build_bitmaps -- the bitmap of every set (Section 3.2, Alg. 3/4/5,
  * precomputed once as in the initialization of Alg. 7).

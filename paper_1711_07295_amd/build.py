@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libssj.so")
 ARCH = os.environ.get("SSJ_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_prepare.hip", "k_sort.hip", "k_bitmap.hip", "k_filter.hip", "k_verify.hip",
+SOURCES = ["k_prepare.hip", "k_sort.hip", "k_bitmap.hip", "k_filter.hip", "k_verify.hip", "k_prefix.hip",
            "ssj_api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

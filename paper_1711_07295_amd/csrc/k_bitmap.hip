@@ -102,7 +102,8 @@ constexpr uint32_t kSegSets = 256;
 template <int WO, int METHOD, bool POW2>
 __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
     const SideDesc *__restrict__ sides, uint32_t n_sides, const uint32_t *__restrict__ rank,
-    uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out, JoinCounters *__restrict__ ctr) {
+    uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out, FoldOut fold,
+    JoinCounters *__restrict__ ctr) {
   __shared__ uint64_t soff[kSegSets + 1];
   __shared__ uint32_t sbits[kSegSets * 2 * WO];
   const SideDesc sd = sides[side_of_block(sides, n_sides, blockIdx.x)];
@@ -138,6 +139,26 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
       out[row * WO + w] = (uint64_t)sbits[x * 2 * WO + 2 * w] |
                           ((uint64_t)sbits[x * 2 * WO + 2 * w + 1] << 32);
   }
+  // Narrower widths b' = b / 2^k from the same pass: bit k' of b' collects
+  // the tokens with t mod b' = k', i.e. bits k' + m b' of b, so word i of b'
+  // combines (xor for Bitmap-Xor, or for Bitmap-Set) words i + m (b'/64).
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const uint32_t wf = (uint32_t)WO >> (f + 1);
+    if (wf == 0 || fold.out[f] == nullptr) continue;
+    for (uint32_t i = threadIdx.x; i < ns * wf; i += kBlock) {
+      const uint32_t x = i / wf, w = i - x * wf;
+      uint64_t v = 0;
+      for (uint32_t m = 0; m < (uint32_t)WO / wf; ++m) {
+        const uint32_t src = w + m * wf;
+        const uint64_t word = (uint64_t)sbits[x * 2 * WO + 2 * src] |
+                              ((uint64_t)sbits[x * 2 * WO + 2 * src + 1] << 32);
+        v = METHOD == SSJ_BM_XOR ? (v ^ word) : (v | word);
+      }
+      const uint64_t row = rank ? rank[sd.base + s0 + x] : sd.base + s0 + x;
+      if (row < n) fold.out[f][row * wf + w] = v;
+    }
+  }
   if (__ballot(unsorted) && (threadIdx.x & 63) == 0) atomicOr(&ctr->error, kErrUnsorted);
 }
 
@@ -169,14 +190,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_bitmaps(const uint64_t *__res
 template <int WO, int METHOD>
 hipError_t launch_seg(bool pow2, hipStream_t st, const SideDesc *sides, uint32_t n_sides,
                       uint32_t seg_blocks, const uint32_t *rank, uint64_t n, uint32_t b_bits,
-                      uint64_t *out, JoinCounters *ctr) {
+                      uint64_t *out, const FoldOut &fold, JoinCounters *ctr) {
   dim3 grid(seg_blocks);
   if (pow2)
     hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, true>), grid, dim3(kBlock), 0, st,
-                       sides, n_sides, rank, n, b_bits, out, ctr);
+                       sides, n_sides, rank, n, b_bits, out, fold, ctr);
   else
     hipLaunchKernelGGL((k_build_bitmaps_seg<WO, METHOD, false>), grid, dim3(kBlock), 0, st,
-                       sides, n_sides, rank, n, b_bits, out, ctr);
+                       sides, n_sides, rank, n, b_bits, out, fold, ctr);
   return hipGetLastError();
 }
 
@@ -184,11 +205,13 @@ template <int METHOD>
 hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint32_t n_sides,
                          uint32_t seg_blocks, uint64_t n, const uint32_t *perm,
                          const uint32_t *rank, const uint32_t *side_of, uint32_t b_bits,
-                         uint32_t out_words, uint64_t *out, JoinCounters *ctr) {
+                         uint32_t out_words, uint64_t *out, const FoldOut &fold,
+                         JoinCounters *ctr) {
   if (METHOD != SSJ_BM_NEXT && (rank || !perm) && seg_blocks) {
-#define SSJ_SEG(wo) \
-  case wo:          \
-    return launch_seg<wo, METHOD>(pow2, st, sides, n_sides, seg_blocks, rank, n, b_bits, out, ctr);
+#define SSJ_SEG(wo)                                                                     \
+  case wo:                                                                              \
+    return launch_seg<wo, METHOD>(pow2, st, sides, n_sides, seg_blocks, rank, n, b_bits, \
+                                  out, fold, ctr);
     switch (out_words) {
       SSJ_SEG(1) SSJ_SEG(2) SSJ_SEG(3) SSJ_SEG(4) SSJ_SEG(5) SSJ_SEG(6) SSJ_SEG(7) SSJ_SEG(8)
       default: break;
@@ -213,21 +236,30 @@ hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_
                                 uint64_t n_total, const uint32_t *perm, const uint32_t *rank,
                                 const uint32_t *side_of, uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
-                                hipStream_t st) {
+                                hipStream_t st, const FoldOut *fold_in) {
   if (n_total == 0) return hipSuccess;
   if (out_words > kMaxWords || out_words < b_bits / 64) return hipErrorInvalidValue;
   if (perm && !side_of) return hipErrorInvalidValue;
+  FoldOut fold{{nullptr, nullptr, nullptr}};
+  if (fold_in) {
+    // folding needs a power-of-two width built at exactly its words, by the
+    // segmented kernel (Xor or Set, at most 8 words)
+    const bool pow2w = (out_words & (out_words - 1)) == 0 && b_bits == 64 * out_words;
+    if (!pow2w || method == SSJ_BM_NEXT || out_words > 8 || !(rank || !perm) || !seg_blocks)
+      return hipErrorInvalidValue;
+    fold = *fold_in;
+  }
   const bool pow2 = (b_bits & (b_bits - 1)) == 0;
   switch (method) {
     case SSJ_BM_XOR:
       return launch_method<SSJ_BM_XOR>(pow2, st, sides, n_sides, seg_blocks, n_total, perm, rank,
-                                       side_of, b_bits, out_words, out, ctr);
+                                       side_of, b_bits, out_words, out, fold, ctr);
     case SSJ_BM_SET:
       return launch_method<SSJ_BM_SET>(pow2, st, sides, n_sides, seg_blocks, n_total, perm, rank,
-                                       side_of, b_bits, out_words, out, ctr);
+                                       side_of, b_bits, out_words, out, fold, ctr);
     case SSJ_BM_NEXT:
       return launch_method<SSJ_BM_NEXT>(pow2, st, sides, n_sides, seg_blocks, n_total, perm,
-                                        rank, side_of, b_bits, out_words, out, ctr);
+                                        rank, side_of, b_bits, out_words, out, fold, ctr);
     default:
       return hipErrorInvalidValue;
   }

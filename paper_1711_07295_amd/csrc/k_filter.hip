@@ -3,28 +3,31 @@
 // For every pair (i, j) of the band it evaluates the overlap bound of
 // Theorem 1 (Eq. 2), UB = floor((|r| + |s| - popcount(b_r xor b_s)) / 2),
 // and keeps the pair when UB reaches the overlap that the threshold needs
-// (Table 1; Alg. 7 without the cutoff, as the paper's GPU algorithm, Alg. 8,
-// runs it).  With L = |r| + |s| and omin(L) the least overlap that reaches
-// t, UB >= omin(L)  <=>  popcount(b_r xor b_s) <= L - 2 omin(L) = slack(L),
-// so each pair costs b/32 xor, b/32 accumulating popcounts and one compare.
+// (Table 1; Alg. 7, as the paper's GPU algorithm, Alg. 8, runs it).  With
+// L = |r| + |s| and omin the least overlap that reaches t,
+// UB >= omin  <=>  popcount(b_r xor b_s) <= L - 2 omin = slack,
+// so each pair costs b/32 xor, b/32 accumulating popcounts and a compare.
 //
 // Work decomposition (size-ordered rows and columns, Section 2.3.2):
-//   - a wave owns 64*R consecutive rows, R per lane, with their bitmaps in
-//     VGPRs for the whole tile;
+//   - a wave owns 64*R consecutive rows of one task, R per lane, with their
+//     bitmaps in VGPRs for the whole tile;
 //   - the wave walks the tile's columns in order; every column's bitmap is
-//     wave-uniform and is read with scalar loads;
+//     wave-uniform and is read with scalar loads, one step of U columns
+//     ahead, into two alternating register buffers;
 //   - columns of equal size form a group; at a group start each lane
 //     derives its threshold from the row and column sizes, folding the
-//     length filter in (threshold -1 = never kept), so the per-pair work is
-//     exactly the xor/popcount/compare;
-//   - the compare lands in a wave mask (ballot); only when some lane keeps a
-//     pair does the wave leave the fast path, reserve queue slots with one
-//     atomic and write the (row, column) pairs at their ballot ranks;
+//     length filter in (threshold -1 = never kept);
+//   - the compare is folded into the popcount: the chain starts at
+//     -(slack + 1), so a kept pair has a negative sum; the sums of a step's
+//     U*R pairs are ORed and one ballot of the sign bit decides whether the
+//     wave leaves the fast path to reserve queue slots and write the kept
+//     (row, column) pairs at their ballot ranks;
 //   - self-join diagonal tiles add the triangle condition j < i.
-// Waves are persistent and take tiles from an atomic cursor.  When the
+// Waves are persistent and take tiles from cursors split per XCD.  When the
 // survivor queue is full the wave marks its reserved slots as sentinels,
-// records (tile, column) to resume from, sets the overflow flag and stops;
-// the host verifies the queue and relaunches with the resume list.
+// records (tile, column, row slab) to resume from, sets the overflow flag
+// and stops; the host verifies the queue and relaunches with the resume
+// list.
 #include <algorithm>
 
 #include "ssj_internal.h"
@@ -452,7 +455,7 @@ hipError_t launch_shape(dim3 grid, hipStream_t st, const FilterArgs &a) {
 
 // Fixed-width kernels: (padded words, rows per lane, columns per step)
 #define SSJ_FILTER_SHAPES(X) \
-  X(1, 2, 8)                 \
+  X(1, 4, 4)                 \
   X(2, 2, 4)                 \
   X(3, 2, 2)                 \
   X(4, 2, 2)                 \

@@ -307,6 +307,45 @@ void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCoun
   ++sp.n_bm;
 }
 
+// Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to 8
+// words come from one pass over the tokens: the widest is built and the
+// narrower ones are folded from it in the same kernel.
+void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits, uint32_t n,
+                         Arena &ar, JoinCounters *ctr, hipStream_t st) {
+  uint32_t need_w[kMaxClasses], need_b[kMaxClasses], m = 0, wmax = 0;
+  bool foldable = sp.rank != nullptr;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (sp.bitmaps(words[k])) continue;
+    need_w[m] = words[k];
+    need_b[m] = bits[k];
+    foldable = foldable && (words[k] & (words[k] - 1)) == 0 && words[k] <= 8 &&
+               bits[k] == 64 * words[k];
+    wmax = std::max(wmax, words[k]);
+    ++m;
+  }
+  if (m == 0) return;
+  if (!foldable || m == 1 || sp.n_bm + m > kMaxClasses) {
+    for (uint32_t k = 0; k < m; ++k) space_bitmaps(sp, need_w[k], need_b[k], ar, ctr, st);
+    return;
+  }
+  FoldOut fold{{nullptr, nullptr, nullptr}};
+  uint64_t *widest = ar.alloc<uint64_t>(sp.n * wmax);
+  for (uint32_t k = 0; k < m; ++k) {
+    uint64_t *dst = widest;
+    if (need_w[k] != wmax) {
+      dst = ar.alloc<uint64_t>(sp.n * need_w[k]);
+      uint32_t f = 0;
+      while ((wmax >> (f + 1)) != need_w[k]) ++f;
+      fold.out[f] = dst;
+    }
+    sp.bm_words[sp.n_bm] = need_w[k];
+    sp.bm[sp.n_bm] = dst;
+    ++sp.n_bm;
+  }
+  check(launch_build_bitmaps(sp.d_sides, sp.n_sides, sp.seg_blocks, sp.n, sp.perm, sp.rank,
+                             sp.side_of, 64 * wmax, SSJ_BM_XOR, wmax, widest, ctr, st, &fold));
+}
+
 // The caller's bitmaps of a one-side space (caller order, bits/64 words),
 // gathered into size order and padded to `words`.
 void space_caller_bitmaps(Space &sp, const uint64_t *bm_caller, uint32_t words, uint32_t bits,
@@ -706,6 +745,7 @@ struct JoinConfig {
   bool tile_cols_fixed = false;  // the caller chose tile_cols
   uint64_t cap = kDefaultQueue;
   bool survivors_only = false;
+  bool cutoff = false;         // rows past the cutoff point take prefix-filtered candidates
   bool cols_resident = false;  // the column space is an index's: no bitmaps are added to it
 };
 
@@ -740,6 +780,29 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       classes[k] = choose_classes(std::max<uint32_t>(a_max, 1), tk.sim, tk.p, tk.q);
     else classes[k].push_back({a_max, wpad});
   }
+  // The cutoff point (Section 3.4) of every task at its widest width: rows
+  // of larger sets skip the bitmap filter and take prefix-filtered
+  // candidates instead.
+  std::vector<uint32_t> omega(n_tasks, 0xFFFFFFFFu);
+  if (jc.cutoff) {
+    for (uint32_t k = 0; k < n_tasks; ++k) {
+      const TaskIn &tk = tasks[k];
+      const uint32_t widest = automatic ? 64 * classes[k].back().words : jc.b_bits;
+      omega[k] = cutoff_point(SSJ_BM_XOR, widest, tk.sim, tk.p, tk.q);
+      if (omega[k] >= R.side_max[tk.row_side]) {
+        omega[k] = 0xFFFFFFFFu;
+        continue;
+      }
+      std::vector<WidthClass> cut;
+      uint32_t prev = 0;
+      for (const auto &c : classes[k]) {
+        if (prev >= omega[k]) break;
+        cut.push_back({std::min(c.max_size, omega[k]), c.words});
+        prev = cut.back().max_size;
+      }
+      classes[k] = cut;
+    }
+  }
   bool any_cosine = false;
   for (const auto &tk : tasks) any_cosine |= tk.sim == SSJ_SIM_COSINE;
   // width slots: every width some task uses, narrowest first
@@ -758,12 +821,15 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     pl.slot_bits[0] = jc.b_bits;
     pl.n_slots = 1;
   }
-  for (uint32_t k = 0; k < pl.n_slots; ++k) {
-    if (!R.bitmaps(pl.slot_words[k])) space_bitmaps(R, pl.slot_words[k], pl.slot_bits[k], ar, ctr, st);
-    if (!C.bitmaps(pl.slot_words[k])) {
-      if (jc.cols_resident) throw Fail{SSJ_E_UNSUPPORTED};
-      space_bitmaps(C, pl.slot_words[k], pl.slot_bits[k], ar, ctr, st);
-    }
+  space_bitmaps_multi(R, pl.slot_words, pl.slot_bits, pl.n_slots, ar, ctr, st);
+  for (uint32_t k = 0; k < pl.n_slots; ++k)
+    if (!C.bitmaps(pl.slot_words[k]) && jc.cols_resident) throw Fail{SSJ_E_UNSUPPORTED};
+  space_bitmaps_multi(C, pl.slot_words, pl.slot_bits, pl.n_slots, ar, ctr, st);
+  if (pl.n_slots == 0) {
+    // no bitmaps (every row past the cutoff): check the token order directly
+    for (const auto &d : R.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
+    if (&C != &R && !jc.cols_resident)
+      for (const auto &d : C.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
   }
   // tiles, slot by slot, task by task.  Unless the caller fixed the tile
   // width, a slot with little work gets narrower tiles, so that it is cut
@@ -802,6 +868,60 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     pl.tile_hi[k] = pl.n_tiles;
     pl.ops[k] = pl.filter_ops - ops0;
   }
+
+  // rows past the cutoff: their band pairs, probe runs and prefix lengths
+  std::vector<PrefixRun> runs;
+  std::vector<uint32_t> ilen;  // [column side][size]: prefix length indexed (0: none)
+  uint64_t n_probe = 0;
+  for (uint32_t k = 0; k < n_tasks; ++k) {
+    if (omega[k] == 0xFFFFFFFFu) continue;
+    const TaskIn &tk = tasks[k];
+    const uint32_t a_max = R.side_max[tk.row_side];
+    uint64_t pb = 0;
+    plan_class(pl, R, C, tk, k, omega[k], a_max, 1, 64, jc.tile_cols, pb, true);
+    pl.band_pairs += pb;
+    task_band[k] += pb;
+    // probe prefix: |r| - omin(|r|, cmin(|r|)) + 1 tokens, the longest any
+    // partner in the band can need (omin grows with the partner's size)
+    const TaskDesc &td = pl.tasks[k];
+    const uint32_t plen_off = (uint32_t)pl.tables.size();
+    for (uint64_t a = 0; a <= a_max; ++a) {
+      uint32_t len = 0;
+      const uint32_t cmn = pl.tables[td.cmin_off + a], cmx = pl.tables[td.cmax_off + a];
+      if (a > omega[k] && cmn <= cmx) {
+        const int64_t o = omin_of(tk.sim, a, cmn, tk.p, tk.q);
+        len = (uint32_t)std::min<int64_t>(std::max<int64_t>((int64_t)a - o + 1, 1), (int64_t)a);
+      }
+      pl.tables.push_back(len);
+    }
+    const uint32_t *rs = R.ss(tk.row_side);
+    PrefixRun run{};
+    run.row_begin = (uint32_t)R.h_sides[tk.row_side].base + rs[omega[k] + 1];
+    run.row_end = (uint32_t)R.h_sides[tk.row_side].base + R.h_sides[tk.row_side].n;
+    run.task = k;
+    run.plen_off = plen_off;
+    run.first = n_probe;
+    if (run.row_end <= run.row_begin) continue;
+    n_probe += run.row_end - run.row_begin;
+    runs.push_back(run);
+    // index prefix of a column of size c: c - omin(a*, c) + 1 tokens, a* the
+    // smallest row size past the cutoff whose band holds c
+    if (ilen.empty()) ilen.assign((size_t)C.n_sides * C.stride, 0);
+    const uint32_t c_max = C.side_max[tk.col_side];
+    for (uint64_t c = 1; c <= c_max; ++c) {
+      uint64_t lo = 0, hi = 0;
+      size_band(tk.sim, c, tk.p, tk.q, lo, hi);  // row sizes that pair with c (Table 2 is symmetric)
+      uint64_t a_lo = std::max<uint64_t>(lo, (uint64_t)omega[k] + 1);
+      if (tk.self) a_lo = std::max<uint64_t>(a_lo, c);
+      if (a_lo > std::min<uint64_t>(hi, a_max)) continue;
+      const int64_t o = omin_of(tk.sim, a_lo, c, tk.p, tk.q);
+      const uint32_t len =
+          (uint32_t)std::min<int64_t>(std::max<int64_t>((int64_t)c - o + 1, 1), (int64_t)c);
+      uint32_t &slot = ilen[(size_t)tk.col_side * C.stride + c];
+      slot = std::max(slot, len);
+    }
+  }
+  if (pl.tables.size() >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
 
   // blocks, tasks, the row sides' tasks and the tables go up in one copy
   constexpr uint64_t kBlockWords = sizeof(RowBlock) / 4, kTaskWords = sizeof(TaskDesc) / 4;
@@ -843,6 +963,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   const VerifySpace vcols{C.d_sides, C.side_of, C.perm, (uint32_t)C.n};
 
   std::deque<Timer> t_filter, t_verify;  // events must not move
+  float prefix_ms_index = 0, prefix_ms_verify = 0;
+  uint64_t prefix_candidates = 0;
   std::vector<uint32_t> t_filter_slot;
   uint32_t n_resume_in = 0;
   uint64_t results_n = 0;
@@ -905,6 +1027,93 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
   }
 
+  // rows past the cutoff: index of column prefixes, probe, deduplicate,
+  // verify, chunk by chunk so that each chunk's candidates fit one queue
+  if (n_probe) {
+    Timer t_index, t_pver;
+    check(hipEventRecord(t_index.ev[0], st));
+    uint32_t *d_ilen = ar.alloc<uint32_t>(ilen.size());
+    h2d(d_ilen, ilen.data(), ilen.size(), st);
+    uint32_t *len = ar.alloc<uint32_t>(C.n);
+    unsigned long long *off = ar.alloc<unsigned long long>(C.n);
+    unsigned long long *d_tot = ar.alloc<unsigned long long>(2);
+    unsigned long long *scan_scr =
+        ar.alloc<unsigned long long>(scan_scratch_words(std::max<uint64_t>(C.n, n_probe)));
+    check(launch_index_len(C.sizes, C.side_of, d_ilen, C.stride, C.n, len, st));
+    check(launch_scan_u32(len, C.n, off, d_tot, scan_scr, st));
+    unsigned long long n_keys = 0;
+    d2h(&n_keys, d_tot, 1, st);
+    sync(st);
+    unsigned long long *keys = ar.alloc<unsigned long long>(n_keys);
+    unsigned long long *ktmp = ar.alloc<unsigned long long>(n_keys);
+    uint32_t *kscr = ar.alloc<uint32_t>(radix_scratch_words(n_keys));
+    check(launch_index_fill(C.d_sides, C.side_of, C.perm, len, off, C.n, keys, st));
+    const int tok_shifts[4] = {32, 40, 48, 56};
+    unsigned long long *sorted_keys = keys;
+    if (n_keys) check(radix_sort_u64(keys, ktmp, n_keys, tok_shifts, 4, kscr, st, &sorted_keys));
+    PrefixRun *d_runs = ar.alloc<PrefixRun>(runs.size());
+    h2d(d_runs, runs.data(), runs.size(), st);
+    const ProbeArgs pa{d_runs, (uint32_t)runs.size(), C.max_size, d_tasks, d_tables, R.sizes,
+                       R.d_sides, R.side_of, R.perm, C.sstart, sorted_keys, n_keys};
+    uint32_t *counts = ar.alloc<uint32_t>(n_probe);
+    unsigned long long *row_off = ar.alloc<unsigned long long>(n_probe);
+    check(launch_probe_count(pa, n_probe, counts, st));
+    check(launch_scan_u32(counts, n_probe, row_off, d_tot + 1, scan_scr, st));
+    std::vector<unsigned long long> off_h(n_probe + 1);
+    d2h(off_h.data(), row_off, n_probe, st);
+    d2h(&off_h[n_probe], d_tot + 1, 1, st);
+    check(hipEventRecord(t_index.ev[1], st));
+    sync(st);
+    uint64_t biggest = 0;
+    for (uint64_t x = 0; x < n_probe; ++x) {
+      const uint64_t c = off_h[x + 1] - off_h[x];
+      if (c >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};  // one row's candidates saturated
+      biggest = std::max(biggest, c);
+    }
+    const uint64_t ccap = std::max<uint64_t>(qcap, biggest);
+    unsigned long long *cand = ar.alloc<unsigned long long>(ccap);
+    unsigned long long *ctmp = ar.alloc<unsigned long long>(ccap);
+    uint32_t *cscr = ar.alloc<uint32_t>(radix_scratch_words(ccap));
+    uint2 *pqueue = ccap > qcap ? ar.alloc<uint2>(ccap) : queue;
+    int cshifts[8], ncs = 0;
+    const int bs = std::max(1, bits_for(C.n ? C.n - 1 : 0)), br = std::max(1, bits_for(R.n ? R.n - 1 : 0));
+    for (int b = 0; b < bs; b += 8) cshifts[ncs++] = b;
+    for (int b = 0; b < br; b += 8) cshifts[ncs++] = 32 + b;
+    check(hipEventRecord(t_pver.ev[0], st));
+    for (uint64_t x0 = 0; x0 < n_probe;) {
+      uint64_t x1 = x0 + 1;
+      while (x1 < n_probe && off_h[x1 + 1] - off_h[x0] <= ccap) ++x1;
+      const uint64_t nc = off_h[x1] - off_h[x0];
+      if (nc) {
+        check(launch_reset_round(ctr, st));
+        check(launch_probe_fill(pa, x0, x1, row_off, off_h[x0], cand, st));
+        unsigned long long *sc = cand;
+        check(radix_sort_u64(cand, ctmp, nc, cshifts, ncs, cscr, st, &sc));
+        check(launch_unique_to_queue(sc, nc, pqueue, ctr, st));
+        if (results_n + nc > res_cap) {
+          const uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + nc);
+          unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
+          check(launch_copy_u64(results, results_n, nr, st));
+          results = nr;
+          res_cap = ncap;
+        }
+        check(launch_verify(pqueue, ccap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
+                            jc.survivors_only ? 1u : 0u, results, res_cap, ctr, st));
+        d2h(&ctr_h, ctr, 1, st);
+        sync(st);
+        if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+        results_n = ctr_h.results;
+        if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};
+      }
+      x0 = x1;
+    }
+    check(hipEventRecord(t_pver.ev[1], st));
+    sync(st);
+    prefix_ms_index = t_index.ms();
+    prefix_ms_verify = t_pver.ms();
+    prefix_candidates = off_h[n_probe];
+  }
+
   // emit: sort the keys (task, i, j) on all their digits, split, copy out
   Timer t_emit;
   check(hipEventRecord(t_emit.ev[0], st));
@@ -947,6 +1156,11 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       stats->class_ms[t_filter_slot[k]] += ms;
     }
     for (auto &t : t_verify) stats->ms_verify += t.ms();
+    // prefix-filtered rows: index and probe count as filtering, the
+    // deduplication and verification of their candidates as verification
+    stats->ms_filter += prefix_ms_index;
+    stats->ms_verify += prefix_ms_verify;
+    (void)prefix_candidates;
     stats->ms_emit = t_emit.ms();
   }
 }
@@ -971,6 +1185,7 @@ JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
   }
   if (opts && opts->queue_capacity) jc.cap = opts->queue_capacity;
   jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
+  jc.cutoff = opts && (opts->flags & SSJ_FLAG_CUTOFF);
   return jc;
 }
 
@@ -1225,7 +1440,9 @@ int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *
       if (b_bits) {
         space_bitmaps(idx->S, wfix, b_bits, idx->ar, ctr, st);
       } else {
-        for (uint32_t w : kAutoWords) space_bitmaps(idx->S, w, 64 * w, idx->ar, ctr, st);
+        uint32_t bits[4];
+        for (int k = 0; k < 4; ++k) bits[k] = 64 * kAutoWords[k];
+        space_bitmaps_multi(idx->S, kAutoWords, bits, 4, idx->ar, ctr, st);
       }
       d2h(&idx->S.ctr_h, ctr, 1, st);
       sync(st);

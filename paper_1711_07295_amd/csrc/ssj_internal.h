@@ -188,11 +188,18 @@ hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uin
 // output is in caller order (row base_s + k for caller set k); with them, in
 // size order (row g for the set perm[g] of side side_of[g]).  The strict
 // token order of every set is checked on the way.
+// fold (optional): also write the widths out_words/2, /4, /8 (out[k] for
+// out_words >> (k+1) words; NULL entries skipped) from the same pass; needs
+// a power-of-two width of at most 8 words, Xor or Set, and the segmented
+// build (caller order, or size order through rank).
+struct FoldOut {
+  uint64_t *out[3];
+};
 hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_t seg_blocks,
                                 uint64_t n_total, const uint32_t *perm, const uint32_t *rank,
                                 const uint32_t *side_of, uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
-                                hipStream_t st);
+                                hipStream_t st, const FoldOut *fold = nullptr);
 // workgroups the segmented build uses for a side of n sets
 uint32_t bitmap_seg_blocks(uint64_t n);
 
@@ -266,6 +273,59 @@ hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace
 hipError_t launch_split_results(const unsigned long long *keys, uint64_t n, int ib, int jb,
                                 uint32_t n_tasks, ssj_pair *out, uint64_t *task_start,
                                 hipStream_t st);
+
+// ------------------------------------------------ prefix-filter candidates
+// Rows [row_begin, row_end) (global row indices) of one task, past its
+// cutoff point; `first` counts the rows of earlier runs, so that run k's
+// rows are probe positions [first, first + row_end - row_begin).
+struct PrefixRun {
+  uint32_t row_begin;
+  uint32_t row_end;
+  uint32_t task;
+  uint32_t plen_off;  // the task's probe prefix-length table (by row size)
+  uint64_t first;
+};
+
+struct ProbeArgs {
+  const PrefixRun *runs;
+  uint32_t n_runs;
+  uint32_t col_max_size;            // largest set size of the column space
+  const TaskDesc *tasks;
+  const uint32_t *tables;
+  const uint32_t *size_rows;
+  const SideDesc *row_sides;
+  const uint32_t *side_of_rows;
+  const uint32_t *perm_rows;
+  const uint32_t *sstart_cols;
+  const unsigned long long *keys;   // sorted index entries (token << 32 | column)
+  uint64_t n_keys;
+};
+
+// Exclusive scan of n uint32 into uint64 offsets; *total = the sum (device).
+// scratch: scan_scratch_words(n) uint64.
+uint64_t scan_scratch_words(uint64_t n);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, unsigned long long *out,
+                           unsigned long long *total, unsigned long long *scratch,
+                           hipStream_t st);
+// len[g] = ilen[side_of[g] * stride + sizes[g]]: prefix length of column g
+hipError_t launch_index_len(const uint32_t *sizes, const uint32_t *side_of, const uint32_t *ilen,
+                            uint32_t stride, uint64_t n, uint32_t *len, hipStream_t st);
+// keys[off[g] + k] = token_k << 32 | g for the first len[g] tokens of column g
+hipError_t launch_index_fill(const SideDesc *sides, const uint32_t *side_of, const uint32_t *perm,
+                             const uint32_t *len, const unsigned long long *off, uint64_t n,
+                             unsigned long long *keys, hipStream_t st);
+// counts[x]: candidates (duplicates included) of probe row x, saturated at
+// 2^32 - 1
+hipError_t launch_probe_count(const ProbeArgs &a, uint64_t n_rows, uint32_t *counts,
+                              hipStream_t st);
+// candidate keys row << 32 | column of probe rows [x0, x1) at
+// out[row_off[x] - base ...]
+hipError_t launch_probe_fill(const ProbeArgs &a, uint64_t x0, uint64_t x1,
+                             const unsigned long long *row_off, unsigned long long base,
+                             unsigned long long *out, hipStream_t st);
+// sorted candidate keys -> distinct queue entries (appended at queue_count)
+hipError_t launch_unique_to_queue(const unsigned long long *keys, uint64_t n, uint2 *queue,
+                                  JoinCounters *ctr, hipStream_t st);
 
 // reset the per-round counters of the queue (not the tile cursors)
 hipError_t launch_reset_round(JoinCounters *ctr, hipStream_t st);

@@ -51,11 +51,12 @@ class ServeResult:
 
 class ContinuousBatcher:
     def __init__(self, index: Index, memory_budget: int = 256 << 20, queue_capacity: int = 0,
-                 keep_pairs: bool = False):
+                 keep_pairs: bool = False, flags: int = 0):
         self.index = index
         self.memory_budget = memory_budget
         self.queue_capacity = queue_capacity
         self.keep_pairs = keep_pairs
+        self.flags = flags
 
     def _call(self, batches, thresholds, device):
         import torch
@@ -74,7 +75,7 @@ class ContinuousBatcher:
             o_at += o.size
             t_at += t.size
         return self.index.query(views, [p for p, _ in thresholds], [q for _, q in thresholds],
-                                queue_capacity=self.queue_capacity)
+                                queue_capacity=self.queue_capacity, flags=self.flags)
 
     def run(self, batches, thresholds, arrivals, device="cuda") -> ServeResult:
         """Serve ``batches`` (host Collections) arriving at ``arrivals``

@@ -255,3 +255,47 @@ def test_selfjoin_10m_row_sample():
     want = oracle.self_join_rows(c.offsets, c.tokens, rows, 4, 5)
     mask = np.isin(got[:, 0], rows) | np.isin(got[:, 1], rows)
     assert np.array_equal(got[mask], want)
+
+
+@pytest.mark.parametrize("pq", [(1, 2), (4, 5)])
+def test_survivors_automatic_widths_match_oracle(pq):
+    """b_bits = 0: every band pair is tested at the width of its row's class
+    (the row is the later set in size order); the bitmaps of the narrower
+    widths are folded from the widest one on the GPU.  The survivor set must
+    equal a brute force over the band with the oracle's bitmaps."""
+    p, q = pq
+    c = gen.generate(n_sets=1500, universe=4000, zipf_s=1.0, size_dist=gen.SIZE_LOGNORMAL,
+                     size_a=60.0, size_b=1.0, size_lo=1, size_hi=700, planted_frac=0.2,
+                     seed=77 + p)
+    got, st = ssj.ssj_self_join(_dev(c), p, q, b_bits=0, flags=ssj.SSJ_FLAG_SURVIVORS_ONLY)
+    ncls = st["n_classes"]
+    assert ncls >= 3
+    bounds, widths = st["class_max_size"][:ncls], st["class_bits"][:ncls]
+    sizes = c.sizes()
+    order = np.lexsort((np.arange(c.n_sets), sizes))     # size order, ties by caller index
+    pos = np.empty(c.n_sets, dtype=np.int64)
+    pos[order] = np.arange(c.n_sets)
+    bms = {b: oracle.bitmaps(c.offsets, c.tokens, b, oracle.BM_XOR) for b in set(widths)}
+    wid = np.array(widths)
+    want = []
+    for i in range(c.n_sets):
+        js = np.arange(i + 1, c.n_sets)
+        a, s = int(sizes[i]), sizes[js]
+        ok = np.array([a > 0 and int(x) > 0 and oracle.length_ok(oracle.JACCARD, a, int(x), p, q)
+                       for x in s], dtype=bool)
+        js = js[ok]
+        if js.size == 0:
+            continue
+        rows = np.where(pos[i] > pos[js], i, js)
+        bw = wid[np.searchsorted(np.array(bounds), sizes[rows])]
+        for b in np.unique(bw):
+            jb = js[bw == b]
+            x = np.bitwise_xor(bms[int(b)][i][None, :], bms[int(b)][jb])
+            h = np.unpackbits(x.view(np.uint8), axis=1).sum(axis=1)
+            for j, hj in zip(jb, h):
+                if oracle.bitmap_survives(a, int(sizes[j]), int(hj), p, q):
+                    want.append((i, int(j)))
+    want.sort()
+    want = np.array(want, dtype=np.uint32).reshape(-1, 2)
+    assert np.array_equal(got, want)
+    assert st["survivors"] == len(want)

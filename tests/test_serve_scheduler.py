@@ -11,7 +11,7 @@ class StubIndex:
     def __init__(self):
         self.calls = []
 
-    def query(self, views, p, q, queue_capacity=0):
+    def query(self, views, p, q, queue_capacity=0, flags=0):
         self.calls.append([(v.n_sets, v.n_tokens) for v in views])
         # one fake pair per set, so the caller's split can be checked
         pairs = [np.stack([np.arange(v.n_sets, dtype=np.uint32)] * 2, axis=1) for v in views]
