@@ -202,6 +202,21 @@ def band_pairs(sizes, p: int, q: int, sim: int = JACCARD) -> int:
     return int(_load().oracle_band_pairs(hist.ctypes.data, mx, sim, p, q))
 
 
+def band_pairs_rs(r_sizes, s_sizes, p: int, q: int, sim: int = JACCARD) -> int:
+    """Pairs (i in R, j in S) of non-empty sets that pass the length filter
+    (Table 2), from the two size histograms."""
+    hr = np.bincount(np.asarray(r_sizes, dtype=np.int64))
+    hs = np.bincount(np.asarray(s_sizes, dtype=np.int64))
+    total = 0
+    for a in range(1, hr.shape[0]):
+        if not hr[a]:
+            continue
+        for c in range(1, hs.shape[0]):
+            if hs[c] and length_ok(sim, a, c, p, q):
+                total += int(hr[a]) * int(hs[c])
+    return total
+
+
 def bitmap(tokens, b: int, method: int = BM_XOR) -> np.ndarray:
     """One set's bitmap, b/64 uint64 words (Alg. 3/4/5, h(t) = t mod b)."""
     lib = _load()

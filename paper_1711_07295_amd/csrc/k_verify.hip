@@ -4,12 +4,18 @@
 // Each queue entry (i, j) names a row and a column (global size-order
 // indices of the row and column spaces); the sets are the caller's CSR sets
 // perm[i] of side side_of[i] and perm[j] of side side_of[j], and the task is
-// the one of the row's side.  The overlap o = |r n s| comes from one sorted
-// merge that stops as soon as even matching every remaining token could not
-// reach omin(|r| + |s|), the least overlap that meets the task's threshold
+// the one of the row's side (of the column's side when the roles of an R-S
+// join are swapped).  The overlap o = |r n s| comes from one sorted merge
+// that stops as soon as even matching every remaining token could not reach
+// omin(|r|, |s|), the least overlap that meets the task's threshold
 // (Table 1, integer form).  A qualifying pair is written as a 64-bit key
 // (task, caller i, caller j), (min, max) for a self-join task and (r, s) for
 // an R-S task, so that one radix sort orders the results of every task.
+//
+// Before the merge, a survivor can be tested once more with wider bitmaps
+// of both sets (the cascade width, the widest a call has built): the bound
+// of Theorem 1 holds at any width, and a wider one prunes most of the false
+// survivors of a narrow class for a few dozen operations.
 //
 // Grid-stride over the queue, one survivor per lane; results are appended
 // with one atomic per wave (ballot + lane rank).
@@ -70,8 +76,8 @@ __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restr
 __global__ __launch_bounds__(kBlock) void k_verify(
     const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
     const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
-    const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only,
-    unsigned long long *__restrict__ results, unsigned long long results_cap,
+    const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only, uint32_t w2,
+    uint32_t by_col, unsigned long long *__restrict__ results, unsigned long long results_cap,
     JoinCounters *__restrict__ ctr) {
   const uint32_t lane = threadIdx.x & 63;
   unsigned long long count = ctr->queue_count;
@@ -92,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
         ++surv;
         const SideDesc dr = rows.sides[rows.side_of[qe.x]];
         const SideDesc dc = cols.sides[cols.side_of[qe.y]];
-        const uint32_t task = side_task[rows.side_of[qe.x]];
+        const uint32_t task = by_col ? side_task[cols.side_of[qe.y]] : side_task[rows.side_of[qe.x]];
         const uint32_t x = rows.perm[qe.x], y = cols.perm[qe.y];
         const uint64_t r0 = dr.offsets[x], r1 = dr.offsets[x + 1];
         const uint64_t s0 = dc.offsets[y], s1 = dc.offsets[y + 1];
@@ -103,11 +109,22 @@ __global__ __launch_bounds__(kBlock) void k_verify(
           const TaskDesc &td = tasks[task];
           const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
                                                          : tables[td.omin_off + a + c];
-          hit = a != 0 && c != 0 && overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
+          // second bitmap test at the cascade width (Theorem 1 holds at
+          // every width): most false survivors of a narrow class end here
+          bool pass = true;
+          if (rows.bm2) {
+            const uint64_t *bx = rows.bm2 + (size_t)qe.x * w2;
+            const uint64_t *by = cols.bm2 + (size_t)qe.y * w2;
+            uint32_t h = 0;
+            for (uint32_t w = 0; w < w2; ++w) h += (uint32_t)__popcll(bx[w] ^ by[w]);
+            pass = (int64_t)h <= (int64_t)a + c - 2 * (int64_t)need;
+          }
+          hit = a != 0 && c != 0 && pass &&
+                overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
         }
         if (hit) {
           uint32_t ki = x, kj = y;
-          if (tasks[task].self && y < x) {
+          if (by_col || (tasks[task].self && y < x)) {
             ki = y;
             kj = x;
           }
@@ -161,11 +178,14 @@ __global__ __launch_bounds__(kBlock) void k_split_results(
 hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
                          VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
                          const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         unsigned long long *results, unsigned long long results_cap,
-                         JoinCounters *ctr, hipStream_t st) {
+                         uint32_t w2, uint32_t by_col, unsigned long long *results,
+                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st) {
+  if ((rows.bm2 == nullptr) != (cols.bm2 == nullptr) || (rows.bm2 && !w2))
+    return hipErrorInvalidValue;
   dim3 grid(filter_grid_blocks());
   hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
-                     tasks, tables, ib, jb, survivors_only, results, results_cap, ctr);
+                     tasks, tables, ib, jb, survivors_only, w2, by_col, results, results_cap,
+                     ctr);
   return hipGetLastError();
 }
 

@@ -255,6 +255,7 @@ struct VerifySpace {
   const SideDesc *sides;
   const uint32_t *side_of;
   const uint32_t *perm;
+  const uint64_t *bm2;     // size-order bitmaps at the cascade width, or NULL
   uint32_t n;              // sets in the space
 };
 
@@ -262,11 +263,14 @@ struct VerifySpace {
 // into 64-bit result keys (task << (ib + jb)) | (i << jb) | j of caller
 // indices (self-join pairs as (min, max)).  side_task[s]: the task of row
 // side s.
+// w2: words of the cascade bitmaps (rows.bm2 and cols.bm2 both set, or
+// both NULL for no second test).  by_col: side_task is indexed by the
+// column side and keys are (task, column caller index, row caller index).
 hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
                          VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
                          const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         unsigned long long *results, unsigned long long results_cap,
-                         JoinCounters *ctr, hipStream_t st);
+                         uint32_t w2, uint32_t by_col, unsigned long long *results,
+                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st);
 
 // Sorted result keys -> ssj_pair {i, j}; task_start[k] = first result of
 // task k (k in [0, n_tasks]).

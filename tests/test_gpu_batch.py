@@ -145,3 +145,37 @@ def test_index_outlives_the_callers_collection_and_edge_cases():
     got, _ = empty.query([_dev(want_rows)], [1], [2])
     assert len(got[0]) == 0
     empty.close()
+
+
+@pytest.mark.parametrize("b", [0, 64, 128])
+def test_rs_join_with_small_r_swaps_roles(b):
+    """|R| * 8 < |S| runs with S as the rows and R as the columns; the pairs
+    are still (i in R, j in S), ascending."""
+    s = _col(900, 4000, universe=600, hi=120, median=20.0, planted=0.3)
+    r = gen.from_lists([s.set(k) for k in range(0, 4000, 60)] +
+                       [_col(901, 50, universe=600, hi=120, median=20.0).set(k) for k in range(50)])
+    assert r.n_sets * 8 < s.n_sets
+    for sim, osim, pq in [(ssj.SSJ_SIM_JACCARD, oracle.JACCARD, (1, 2)),
+                          (ssj.SSJ_SIM_JACCARD, oracle.JACCARD, (4, 5)),
+                          (ssj.SSJ_SIM_COSINE, oracle.COSINE, (7, 10))]:
+        p, q = pq
+        want = oracle.rs_join(r.offsets, r.tokens, s.offsets, s.tokens, p, q, sim=osim)
+        for flags in (0, ssj.SSJ_FLAG_CUTOFF):
+            got, st = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=b, sim=sim, flags=flags)
+            assert np.array_equal(got, want), (b, sim, p, q, flags)
+            assert st["band_pairs"] == oracle.band_pairs_rs(r.sizes(), s.sizes(), p, q, sim=osim)
+
+
+def test_index_small_batches_swap_roles():
+    sw = gen.served_workload(6, resident_sets=8000, max_batch=60, seed=gen.SEED_BASE + 41)
+    res = sw.resident
+    with ssj.Index(_dev(res)) as idx:
+        devs = [_dev(x) for x in sw.batches]
+        ps, qs = [t[0] for t in sw.thresholds], [t[1] for t in sw.thresholds]
+        got, _ = idx.query(devs, ps, qs)
+        for x, p, q, g in zip(sw.batches, ps, qs, got):
+            want = oracle.rs_join(x.offsets, x.tokens, res.offsets, res.tokens, p, q)
+            assert np.array_equal(g, want)
+        got_cut, _ = idx.query(devs, ps, qs, flags=ssj.SSJ_FLAG_CUTOFF)
+        for a, b in zip(got, got_cut):
+            assert np.array_equal(a, b)

@@ -168,3 +168,14 @@ def test_check_pairs_agrees_with_join():
     cand = cand[cand[:, 0] < cand[:, 1]]
     ok = oracle.check_pairs(c.offsets, c.tokens, c.offsets, c.tokens, cand, 3, 5)
     assert ok.tolist() == [tuple(x) in found for x in cand.tolist()]
+
+
+def test_band_pairs_rs_bruteforce():
+    rng = np.random.default_rng(5)
+    r = rng.integers(0, 30, size=60)
+    s = rng.integers(0, 30, size=80)
+    for sim in (oracle.JACCARD, oracle.DICE, oracle.COSINE):
+        for p, q in ((1, 2), (4, 5), (1, 1)):
+            want = sum(1 for a in r for c in s
+                       if a and c and oracle.length_ok(sim, int(a), int(c), p, q))
+            assert oracle.band_pairs_rs(r, s, p, q, sim=sim) == want
