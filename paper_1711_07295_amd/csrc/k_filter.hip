@@ -20,14 +20,15 @@
 //   - the compare is folded into the popcount: the chain starts at
 //     -(slack + 1), so a kept pair has a negative sum; the sums of a step's
 //     U*R pairs are ORed and one ballot of the sign bit decides whether the
-//     wave leaves the fast path to reserve queue slots and write the kept
-//     (row, column) pairs at their ballot ranks;
+//     wave leaves the fast path to stage the kept (row, column) pairs at
+//     their ballot ranks in its LDS buffer, which goes to the queue with one
+//     reservation when full and at the end of every tile;
 //   - self-join diagonal tiles add the triangle condition j < i.
 // Waves are persistent and take tiles from cursors split per XCD.  When the
 // survivor queue is full the wave marks its reserved slots as sentinels,
-// records (tile, column, row slab) to resume from, sets the overflow flag
-// and stops; the host verifies the queue and relaunches with the resume
-// list.
+// records (tile, column, row slab) of its first staged pair to resume from,
+// sets the overflow flag and stops; the host verifies the queue and
+// relaunches with the resume list.
 #include <algorithm>
 
 #include "ssj_internal.h"
@@ -51,22 +52,54 @@ struct Rows {
   uint32_t idx[R];
 };
 
+// Kept pairs are staged per wave in LDS and written to the queue in runs:
+// one queue reservation per run instead of one per (column, row slab) mask,
+// since same-address atomics from every XCD serialise.  A run never spans
+// tiles, so the first staged entry always names a point of the current tile.
+constexpr uint32_t kStage = 256;
+
 struct Sink {
   uint2 *queue;
   JoinCounters *ctr;
   unsigned long long cap;
-  uint32_t fail_col;   // set by the slow path when the queue fills
+  uint2 *stage;         // this wave's kStage LDS entries
+  uint32_t fill;        // entries staged (wave-uniform)
+  uint32_t first_col;   // (column, row slab) of the first staged entry
+  uint32_t first_slab;
+  uint32_t fail_col;    // resume point, set when the queue fills
   uint32_t fail_slab;
 };
+
+// Reserve queue slots for the staged entries and copy them out.  When they
+// do not fit, the reserved slots that exist become sentinels, the first
+// staged entry's point is left as the resume point and false is returned:
+// every pair before that point is in the queue, none after it.
+__device__ __forceinline__ bool flush(Sink &s) {
+  const uint32_t n = rfl(s.fill);
+  if (n == 0) return true;
+  const uint32_t lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&s.ctr->queue_count, (unsigned long long)n);
+  base = rfl64(base);
+  const bool fits = base + n <= s.cap;
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t x = lane; x < n; x += 64) {
+    const unsigned long long pos = base + x;
+    if (pos < s.cap) s.queue[pos] = fits ? s.stage[x] : make_uint2(kSentinel, kSentinel);
+  }
+  __builtin_amdgcn_wave_barrier();
+  s.fill = 0;
+  if (!fits) {
+    s.fail_col = s.first_col;
+    s.fail_slab = s.first_slab;
+    return false;
+  }
+  return true;
+}
 
 // popcount(x) + acc as one v_bcnt_u32_b32.  Written out so that the sum over
 // a bitmap's words stays one accumulating chain (the compiler would otherwise
 // split it into parallel chains joined by an extra add).
-__device__ __forceinline__ uint32_t bcnt_first(uint32_t x) {
-  uint32_t r;
-  asm("v_bcnt_u32_b32 %0, %1, 0" : "=v"(r) : "v"(x));
-  return r;
-}
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
   uint32_t r;
   asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
@@ -86,80 +119,30 @@ __device__ __forceinline__ uint32_t biased_distance(const Rows<W, R> &rw, const 
   return h;
 }
 
-// Whether some (column u, row r) pair of a step is kept: the OR of the
-// biased distances has its sign bit set.
+// Slow path: stage the kept pairs of columns [j, j+U), one (column, row
+// slab) mask at a time in (column, slab) order, from the biased distances
+// the step computed.  False when the queue filled (resume point in the
+// sink).
 template <int W, int R, int U>
-__device__ __forceinline__ bool step_any(const Rows<W, R> &rw, const uint32_t (&cb)[U][2 * W],
-                                         const uint32_t (&bias)[R]) {
-  uint32_t acc = 0;
+__device__ __forceinline__ bool emit(const Rows<W, R> &rw, const uint32_t (&d)[U][R], uint32_t j,
+                                     Sink &sink) {
+  const unsigned long long below = __lanemask_lt();
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc |= biased_distance<W, R>(rw, cb[u], r, bias[r]);
-  return __ballot((int32_t)acc < 0) != 0;
-}
-
-template <int W, int R, bool DIAG>
-__device__ __forceinline__ bool keep(const Rows<W, R> &rw, const uint32_t *cb, int r,
-                                     int32_t thr, uint32_t j) {
-  uint32_t h = bcnt_first(rw.bits[r][0] ^ cb[0]);
-#pragma unroll
-  for (int e = 1; e < 2 * W; ++e) h = bcnt_acc(rw.bits[r][e] ^ cb[e], h);
-  bool k = (int32_t)h <= thr;
-  if (DIAG) k = k && (j < rw.idx[r]);
-  return k;
-}
-
-// Slow path: write the kept pairs of columns [j, j+U), one (column, row
-// slab) mask at a time, each with its own queue reservation.  It is rare,
-// so it reloads the bitmaps it needs instead of keeping the fast path's
-// values alive, and it does not unroll: its registers stay few.  When a
-// reservation does not fit, its slots become sentinels, the point reached
-// (column, row slab) is left in the sink and false is returned; every mask
-// before that point has been written.
-template <int W, int R, int U, bool DIAG>
-__device__ __forceinline__ bool emit(const uint64_t *__restrict__ bm_rows,
-                                     const uint64_t *__restrict__ bm_cols, uint32_t row0,
-                                     uint32_t row_end, const int32_t (&thr)[R], uint32_t j,
-                                     Sink &sink) {
-  const uint32_t lane = threadIdx.x & 63;
-  const unsigned long long below = __lanemask_lt();
-#pragma unroll 1
-  for (uint32_t k = 0; k < (uint32_t)(U * R); ++k) {
-    const uint32_t u = k / R, r = k - (k / R) * R;
-    const uint32_t i = row0 + 64u * r + lane, col = j + u;
-    int32_t t = thr[0];
-#pragma unroll
-    for (int rr = 1; rr < R; ++rr)
-      if (r == (uint32_t)rr) t = thr[rr];
-    bool kp = false;
-    if (i < row_end) {
-      const uint32_t *rb = reinterpret_cast<const uint32_t *>(bm_rows + (size_t)i * W);
-      const uint32_t *cbp = reinterpret_cast<const uint32_t *>(bm_cols + (size_t)col * W);
-      int32_t h = 0;
-#pragma unroll
-      for (int e = 0; e < 2 * W; ++e) h += __builtin_popcount(rb[e] ^ cbp[e]);
-      kp = h <= t && (!DIAG || col < i);
+    for (int r = 0; r < R; ++r) {
+      const bool kp = (int32_t)d[u][r] < 0;
+      const unsigned long long m = __ballot(kp);
+      if (!m) continue;
+      const uint32_t cnt = (uint32_t)__popcll(m);
+      if (sink.fill + cnt > kStage && !flush(sink)) return false;
+      if (sink.fill == 0) {
+        sink.first_col = j + u;
+        sink.first_slab = r;
+      }
+      if (kp) sink.stage[sink.fill + (uint32_t)__popcll(m & below)] = make_uint2(rw.idx[r], j + u);
+      sink.fill += cnt;
     }
-    const unsigned long long m = __ballot(kp);
-    if (!m) continue;
-    const uint32_t cnt = (uint32_t)__popcll(m);
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&sink.ctr->queue_count, (unsigned long long)cnt);
-    base = rfl64(base);
-    const bool fits = base + cnt <= sink.cap;
-    if (kp) {
-      const unsigned long long pos = base + (unsigned long long)__popcll(m & below);
-      if (pos < sink.cap)
-        sink.queue[pos] = fits ? make_uint2(i, col) : make_uint2(kSentinel, kSentinel);
-    }
-    if (!fits) {
-      // the wave's main loop records (tile, column, slab) for resumption
-      sink.fail_col = col;
-      sink.fail_slab = r;
-      return false;
-    }
-  }
   return true;
 }
 
@@ -191,35 +174,34 @@ __device__ __forceinline__ uint32_t after(uint32_t j) {
   return j;
 }
 
-// One step: columns [j, j + U) against the wave's rows; the slow path
-// writes the kept pairs.  False when the queue filled.
+// One step: columns [j, j + U) against the wave's rows.  The biased
+// distances of its U*R pairs are ORed and one ballot of the sign bit tells
+// whether any is kept; only then does the slow path stage them.  On a
+// diagonal tile a pair off the lower triangle (j >= i) is made positive.
+// False when the queue filled.
 template <int W, int R, int U, bool DIAG>
-__device__ __forceinline__ bool step(const uint64_t *__restrict__ bm_rows,
-                                     const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
-                                     uint32_t row0, uint32_t row_end, const int32_t (&thr)[R],
-                                     const uint32_t (&bias)[R], const uint32_t (&cb)[U][2 * W],
-                                     uint32_t j, Sink &sink) {
-  bool any;
-  if (DIAG) {
-    unsigned long long m = 0;
+__device__ __forceinline__ bool step(const Rows<W, R> &rw, const uint32_t (&bias)[R],
+                                     const uint32_t (&cb)[U][2 * W], uint32_t j, Sink &sink) {
+  uint32_t d[U][R];
+  uint32_t acc = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int r = 0; r < R; ++r) m |= __ballot(keep<W, R, DIAG>(rw, cb[u], r, thr[r], j + u));
-    any = m != 0;
-  } else {
-    any = step_any<W, R, U>(rw, cb, bias);
-  }
-  if (any) return emit<W, R, U, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink);
+    for (int r = 0; r < R; ++r) {
+      uint32_t h = biased_distance<W, R>(rw, cb[u], r, bias[r]);
+      if (DIAG) h = j + u < rw.idx[r] ? h : 0u;
+      d[u][r] = h;
+      acc |= h;
+    }
+  if (__ballot((int32_t)acc < 0)) return emit<W, R, U>(rw, d, j, sink);
   return true;
 }
 
 // Columns [j, g1) of one size group.
 template <int W, int R, int U, bool DIAG>
-__device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_rows,
-                                      const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
-                                      uint32_t row0, uint32_t row_end, const int32_t (&thr)[R],
-                                      uint32_t j, uint32_t g1, Sink &sink) {
+__device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_cols, const Rows<W, R> &rw,
+                                      const int32_t (&thr)[R], uint32_t j, uint32_t g1,
+                                      Sink &sink) {
   uint32_t bias[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) bias[r] = (uint32_t)(-thr[r] - 1);
@@ -235,27 +217,18 @@ __device__ __forceinline__ bool sweep(const uint64_t *__restrict__ bm_rows,
     if (j + U > g1) break;
     const uint32_t jb = after(j + U);
     if (jb + U <= g1) load_cols<W, U>(bm_cols, jb, bb);
-    if (!step<W, R, U, DIAG>(bm_rows, bm_cols, rw, row0, row_end, thr, bias, ba, j, sink))
-      return false;
+    if (!step<W, R, U, DIAG>(rw, bias, ba, j, sink)) return false;
     j += U;
     if (j + U > g1) break;
     const uint32_t ja = after(j + U);
     if (ja + U <= g1) load_cols<W, U>(bm_cols, ja, ba);
-    if (!step<W, R, U, DIAG>(bm_rows, bm_cols, rw, row0, row_end, thr, bias, bb, j, sink))
-      return false;
+    if (!step<W, R, U, DIAG>(rw, bias, bb, j, sink)) return false;
     j += U;
   }
   for (; j < g1; ++j) {
     uint32_t cb[1][2 * W];
-    const_u32_ptr p = as_const(bm_cols + (size_t)j * W);
-#pragma unroll
-    for (int e = 0; e < 2 * W; ++e) cb[0][e] = p[e];
-    unsigned long long any = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) any |= __ballot(keep<W, R, DIAG>(rw, cb[0], r, thr[r], j));
-    if (any) {
-      if (!emit<W, R, 1, DIAG>(bm_rows, bm_cols, row0, row_end, thr, j, sink)) return false;
-    }
+    load_cols<W, 1>(bm_cols, j, cb);
+    if (!step<W, R, 1, DIAG>(rw, bias, cb, j, sink)) return false;
   }
   return true;
 }
@@ -316,13 +289,14 @@ __device__ __forceinline__ bool run_tile(
     first_slab = 0;
     if (__ballot(any_ok)) {
       const bool ok =
-          diag ? sweep<W, R, U, true>(bm_rows, bm_cols, rw, row0, row_end, thr, j, gend, sink)
-               : sweep<W, R, U, false>(bm_rows, bm_cols, rw, row0, row_end, thr, j, gend, sink);
+          diag ? sweep<W, R, U, true>(bm_cols, rw, thr, j, gend, sink)
+               : sweep<W, R, U, false>(bm_cols, rw, thr, j, gend, sink);
       if (!ok) return false;
     }
     j = gend;
   }
-  return true;
+  // the tile's staged pairs go out before the next tile
+  return flush(sink);
 }
 
 // Persistent filter for one bitmap width (W words, R rows per lane, U
@@ -341,10 +315,15 @@ __global__ __launch_bounds__(kBlock) void k_filter(
     const Resume *__restrict__ resume_in, Resume *__restrict__ resume_out, FilterConfig cfg) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = rfl(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+  __shared__ uint2 stage[kBlock / 64][kStage];
   Sink sink;
   sink.queue = queue;
   sink.ctr = ctr;
   sink.cap = cfg.cap;
+  sink.stage = stage[threadIdx.x >> 6];
+  sink.fill = 0;
+  sink.first_col = 0;
+  sink.first_slab = 0;
   sink.fail_col = 0;
   sink.fail_slab = 0;
 
