@@ -30,7 +30,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_INT_OPS = 256 * 64 * 2.4e9   # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_FP4 = 10.1e15                # dense fp4 MFMA flop/s (published)
 PEAK_HBM = 8.0e12                 # bytes/s
+MFMA_BITS = (64, 128, 256, 512)   # widths the matrix-core filter runs
 
 # HBM bytes per launch of the dominant filter launch (the b = 64 class of the
 # 1,000,000-set workload at 4/5), from two rocprofv3 --pmc passes (FETCH_SIZE,
@@ -102,6 +104,9 @@ def main():
     ap.add_argument("--tile-cols", type=int, default=0, help="0 = the library default")
     ap.add_argument("--cutoff", action="store_true",
                     help="rows past the cutoff point take prefix-filtered candidates")
+    ap.add_argument("--valu", action="store_true",
+                    help="vector-ALU filter at every width (SSJ_FLAG_VALU) instead of the "
+                         "matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (reference for the "
@@ -139,7 +144,7 @@ def main():
     dev = ssj.to_device(col.offsets, col.tokens)
     torch.cuda.synchronize()
 
-    flags = ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0
+    flags = (ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0) | (ssj.SSJ_FLAG_VALU if args.valu else 0)
     sim = {"jaccard": ssj.SSJ_SIM_JACCARD, "dice": ssj.SSJ_SIM_DICE,
            "cosine": ssj.SSJ_SIM_COSINE, "overlap": ssj.SSJ_SIM_OVERLAP}[args.sim]
 
@@ -174,10 +179,10 @@ def main():
     # work per class, and times every launch with events on its stream.
     s0 = stats[0]
     ncls = s0["n_classes"]
-    roof = roofline_of(stats, args.steps)
+    roof = roofline_of(stats, args.steps, args.valu)
     dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
     if (args.workload == "selfjoin-1m" and (args.p, args.q) == (4, 5) and args.bits == 0
-            and args.sim == "jaccard" and s0["class_bits"][dom] == 64):
+            and args.sim == "jaccard" and s0["class_bits"][dom] == 64 and not args.valu):
         roof["traffic"] = traffic_bytes()
     classes = [{"max_set_size": m, "b_bits": b, "ops": o, "ms": sum(s["class_ms"][k]
                 for s in stats) / args.steps}
@@ -191,7 +196,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
                    "threshold": f"{args.p}/{args.q}", "similarity": args.sim,
-                   "cutoff": args.cutoff,
+                   "cutoff": args.cutoff, "filter": "valu" if args.valu else "mfma",
                    "b_bits": args.bits if args.bits else "auto", "width_classes": classes,
                    "generator": "Bitmap-Xor",
                    "band_pairs": band, "results": stats[0]["results"],
@@ -210,23 +215,40 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def roofline_of(stats_list, steps):
+def roofline_of(stats_list, steps, valu=False):
     """Roofline entry of the dominant filter launch (the width class with the
-    most algorithmic work), from the library's per-class event timings."""
+    most algorithmic work), from the library's per-class event timings.
+
+    Matrix-core kernel (b = 64..512): per band pair the contraction of two
+    +-1 vectors of b entries, 2b fp4 flops, against the dense fp4 peak.
+    Vector-ALU kernel: per band pair b/32 xor + b/32 popcount-accumulate + 1
+    compare, int32 lane-ops against the vector ALU peak (the library's
+    filter_ops)."""
     s0 = stats_list[0]
     ncls = s0["n_classes"]
     dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
+    b = s0["class_bits"][dom]
     dom_ms = sum(s["class_ms"][dom] for s in stats_list) / steps
     launches = sum(s["filter_launches"] for s in stats_list) / steps / ncls
-    achieved = s0["class_ops"][dom] / (dom_ms / 1e3)
     filt_ms = sum(s["ms_filter"] for s in stats_list) / steps
+    band = s0["class_ops"][dom] / (b // 16 + 1)  # band pairs of the class
+    stage = {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
+             "valu_equiv_frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}
+    if b in MFMA_BITS and not valu:
+        achieved = band * 2 * b / (dom_ms / 1e3)
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP4 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP4, "traffic": None,
+                "kernel": f"k_filter_mfma (b = {b} class, fp4 +-1 dot products)",
+                "flops_per_launch": band * 2 * b / launches,
+                "band_pairs_per_launch": band / launches, "avg_launch_ms": dom_ms / launches,
+                "filter_stage": stage}
+    achieved = s0["class_ops"][dom] / (dom_ms / 1e3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
             "unit": "Top/s", "frac": achieved / PEAK_INT_OPS, "traffic": None,
-            "kernel": f"k_filter (b = {s0['class_bits'][dom]} class)",
+            "kernel": f"k_filter (b = {b} class, vector ALU)",
             "ops_per_launch": s0["class_ops"][dom] / launches,
-            "avg_launch_ms": dom_ms / launches,
-            "filter_stage": {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
-                             "frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}}
+            "band_pairs_per_launch": band / launches, "avg_launch_ms": dom_ms / launches,
+            "filter_stage": stage}
 
 
 def run_batch(args):

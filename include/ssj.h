@@ -140,6 +140,13 @@ typedef struct {
  * SSJ_FLAG_SURVIVORS_ONLY those rows report their prefix candidates. */
 #define SSJ_FLAG_CUTOFF 2u
 
+/* Run the bitmap filter on the vector ALUs at every width.  By default the
+ * widths b = 64, 128, 256 and 512 run on the matrix cores, which score the
+ * Hamming distance of Theorem 1 as a dot product of +-1 vectors (exact);
+ * the two kernels keep the same pairs.  Changes the work, never the
+ * result. */
+#define SSJ_FLAG_VALU 4u
+
 /*
  * ssj_build_bitmaps -- the bitmap of every set (Section 3.2, Alg. 3/4/5,
  * precomputed once as in the initialization of Alg. 7).

@@ -18,6 +18,9 @@ SOURCES = ["k_prepare.hip", "k_sort.hip", "k_bitmap.hip", "k_filter.hip", "k_ver
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off (no float math here anyway)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results in VGPRs: the filter reads every one of them
+         # with vector ALU ops, and AGPR results would each cost a copy
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

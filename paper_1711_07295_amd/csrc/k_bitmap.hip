@@ -228,6 +228,34 @@ hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint3
   return hipGetLastError();
 }
 
+// Sign planes: one thread per (set, 64-bit block, half), for n + 1 sets: set
+// n is all zero.  Each half of 32 bits becomes four dwords of fp4 nibbles,
+// +1 (0x2) for a set bit and -1 (0xA) for a clear one.
+__global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restrict__ bm,
+                                                          uint32_t words, uint64_t n,
+                                                          uint4 *__restrict__ planes) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (n + 1) * words * 2) return;
+  const uint32_t h = (uint32_t)(t & 1);
+  const uint64_t sw = t >> 1;
+  const uint64_t s = sw / words;
+  const uint32_t kb = (uint32_t)(sw - s * words);
+  uint4 out = make_uint4(0u, 0u, 0u, 0u);
+  if (s < n) {
+    const uint32_t x = (uint32_t)(bm[sw] >> (32 * h));
+    uint32_t d[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      uint32_t spread = 0;  // bit m of byte e at bit 4m
+#pragma unroll
+      for (int m = 0; m < 8; ++m) spread |= ((x >> (8 * e + m)) & 1u) << (4 * m);
+      d[e] = 0xAAAAAAAAu ^ (spread << 3);
+    }
+    out = make_uint4(d[0], d[1], d[2], d[3]);
+  }
+  planes[((uint64_t)kb * (n + 1) + s) * 2 + h] = out;
+}
+
 }  // namespace
 
 uint32_t bitmap_seg_blocks(uint64_t n) { return (uint32_t)((n + kSegSets - 1) / kSegSets); }
@@ -281,6 +309,15 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
   dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
   hipLaunchKernelGGL(k_gather_bitmaps, grid, dim3(kBlock), 0, st, in, perm, n, in_words,
                      out_words, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
+                               hipStream_t st) {
+  if (words == 0) return hipErrorInvalidValue;
+  const uint64_t total = (n + 1) * words * 2;
+  hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, st, bm, words, n, planes);
   return hipGetLastError();
 }
 

@@ -52,48 +52,67 @@ struct Rows {
   uint32_t idx[R];
 };
 
-// Kept pairs are staged per wave in LDS and written to the queue in runs:
-// one queue reservation per run instead of one per (column, row slab) mask,
-// since same-address atomics from every XCD serialise.  A run never spans
-// tiles, so the first staged entry always names a point of the current tile.
-constexpr uint32_t kStage = 256;
+// Kept pairs are staged per wave in LDS and written to the queue in runs.
+// Queue slots come from a chunk the wave reserves for itself (cfg.chunk
+// slots per reservation), so reservations are few: same-address atomics
+// from every XCD serialise at the memory side, and one per run would cost
+// more than the filter.  A run never spans tiles, so the first staged entry
+// always names a point of the current tile.  The unused end of a chunk is
+// filled with sentinels (verification skips them) when the wave takes a
+// new chunk and when it exits.
+constexpr uint32_t kStage = kFilterStage;
 
 struct Sink {
   uint2 *queue;
   JoinCounters *ctr;
   unsigned long long cap;
-  uint2 *stage;         // this wave's kStage LDS entries
-  uint32_t fill;        // entries staged (wave-uniform)
-  uint32_t first_col;   // (column, row slab) of the first staged entry
+  uint32_t chunk;              // slots per reservation (>= kStage)
+  uint2 *stage;                // this wave's kStage LDS entries
+  uint32_t fill;               // entries staged (wave-uniform)
+  uint32_t first_col;          // (column, row slab) of the first staged entry
   uint32_t first_slab;
-  uint32_t fail_col;    // resume point, set when the queue fills
+  uint32_t fail_col;           // resume point, set when the queue fills
   uint32_t fail_slab;
+  unsigned long long pos, end; // the wave's reserved slots [pos, end), end <= cap
 };
 
-// Reserve queue slots for the staged entries and copy them out.  When they
-// do not fit, the reserved slots that exist become sentinels, the first
-// staged entry's point is left as the resume point and false is returned:
-// every pair before that point is in the queue, none after it.
+// Sentinels into the rest of the wave's chunk.
+__device__ __forceinline__ void sink_pad(Sink &s) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (unsigned long long x = s.pos + lane; x < s.end; x += 64)
+    s.queue[x] = make_uint2(kSentinel, kSentinel);
+  s.pos = s.end;
+}
+
+// Copy the staged entries into the wave's chunk, reserving a new chunk
+// when they do not fit in the current one.  When the queue has no room
+// for them, the reserved slots become sentinels, the first staged entry's
+// point is left as the resume point and false is returned: every pair
+// before that point is in the queue, none after it.
 __device__ __forceinline__ bool flush(Sink &s) {
   const uint32_t n = rfl(s.fill);
   if (n == 0) return true;
   const uint32_t lane = threadIdx.x & 63;
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&s.ctr->queue_count, (unsigned long long)n);
-  base = rfl64(base);
-  const bool fits = base + n <= s.cap;
-  __builtin_amdgcn_wave_barrier();
-  for (uint32_t x = lane; x < n; x += 64) {
-    const unsigned long long pos = base + x;
-    if (pos < s.cap) s.queue[pos] = fits ? s.stage[x] : make_uint2(kSentinel, kSentinel);
+  if (s.pos + n > s.end) {
+    sink_pad(s);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&s.ctr->queue_count, (unsigned long long)s.chunk);
+    base = rfl64(base);
+    s.pos = base < s.cap ? base : s.cap;
+    s.end = base + s.chunk < s.cap ? base + s.chunk : s.cap;
+    if (s.pos + n > s.end) {
+      sink_pad(s);
+      s.fill = 0;
+      s.fail_col = s.first_col;
+      s.fail_slab = s.first_slab;
+      return false;
+    }
   }
   __builtin_amdgcn_wave_barrier();
+  for (uint32_t x = lane; x < n; x += 64) s.queue[s.pos + x] = s.stage[x];
+  __builtin_amdgcn_wave_barrier();
+  s.pos += n;
   s.fill = 0;
-  if (!fits) {
-    s.fail_col = s.first_col;
-    s.fail_slab = s.first_slab;
-    return false;
-  }
   return true;
 }
 
@@ -299,34 +318,36 @@ __device__ __forceinline__ bool run_tile(
   return flush(sink);
 }
 
-// Persistent filter for one bitmap width (W words, R rows per lane, U
-// columns per step) over the tiles [cfg.tile_lo, cfg.tile_hi) of the plan.
-// Waves first take the resume entries of a previous launch that fall in
-// that range (entry k goes to wave k), then tiles from the partitioned
-// cursors, until the range is exhausted or the queue has filled.
-template <int W, int R, int U, bool COS>
-__global__ __launch_bounds__(kBlock) void k_filter(
-    const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
-    const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
-    const uint32_t *__restrict__ sstart_cols, const uint32_t *__restrict__ tables,
-    const TaskDesc *__restrict__ tasks, const RowBlock *__restrict__ blocks,
-    const uint32_t *__restrict__ tile_block,
-    uint2 *__restrict__ queue, JoinCounters *__restrict__ ctr,
-    const Resume *__restrict__ resume_in, Resume *__restrict__ resume_out, FilterConfig cfg) {
+// What a wave needs to run one tile.
+struct TileJob {
+  uint32_t row0, row_end, c0, c1;
+  bool diag;
+  uint32_t first;  // resumed inside the tile: first slab (vector ALU) or pairs to skip (MFMA)
+  const int32_t *slack;
+  const uint32_t *cmin, *cmax, *sstart;
+  uint32_t col_base;
+  bool cosine;
+  uint32_t p, q;
+};
+
+// The persistent loop both kernels share, over the tiles [cfg.tile_lo,
+// cfg.tile_hi) of the plan.  Waves first take the resume entries of a
+// previous launch that fall in that range (entry k goes to wave k), then
+// tiles from the partitioned cursors, until the range is exhausted or the
+// queue has filled.  run(job) runs one tile and returns false when the
+// queue filled, with the resume point in the sink.
+template <class Run>
+__device__ __forceinline__ void persistent(const uint32_t *__restrict__ tables,
+                                           const TaskDesc *__restrict__ tasks,
+                                           const RowBlock *__restrict__ blocks,
+                                           const uint32_t *__restrict__ tile_block,
+                                           const uint32_t *__restrict__ sstart_cols,
+                                           JoinCounters *__restrict__ ctr,
+                                           const Resume *__restrict__ resume_in,
+                                           Resume *__restrict__ resume_out,
+                                           const FilterConfig &cfg, Sink &sink, Run &&run) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = rfl(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
-  __shared__ uint2 stage[kBlock / 64][kStage];
-  Sink sink;
-  sink.queue = queue;
-  sink.ctr = ctr;
-  sink.cap = cfg.cap;
-  sink.stage = stage[threadIdx.x >> 6];
-  sink.fill = 0;
-  sink.first_col = 0;
-  sink.first_slab = 0;
-  sink.fail_col = 0;
-  sink.fail_slab = 0;
-
   bool resumed = false;
   uint32_t t = 0, col = 0, slab = 0;
   if (wave < cfg.n_resume_in && wave < cfg.resume_cap) {
@@ -337,14 +358,20 @@ __global__ __launch_bounds__(kBlock) void k_filter(
   }
   const uint32_t n_tiles = cfg.tile_hi - cfg.tile_lo;
   uint32_t *cursors = &ctr->tile_next[cfg.cls][0][0];
-  // Workgroups are dispatched to the XCDs round-robin: start in this XCD's
-  // partition of the tile range, move on to the others when it runs dry.
-  uint32_t part = blockIdx.x % kParts, parts_left = kParts;
+  // The tile range is cut into kParts partitions with a cursor each, so that
+  // the cursors' atomics spread over many addresses.  Workgroups are
+  // dispatched to the XCDs round-robin: a workgroup starts in a partition of
+  // its own XCD (p mod kXcds), takes that XCD's other partitions next, and
+  // only then the rest.
+  const uint32_t base_part = blockIdx.x % kParts;
+  uint32_t visit = 0;
   for (;;) {
     if (!resumed) {
-      if (__hip_atomic_load(&ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+      if (__hip_atomic_load(&ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       bool got = false;
-      while (parts_left) {
+      while (visit < kParts) {
+        const uint32_t part =
+            (base_part + kXcds * (visit % (kParts / kXcds)) + visit / (kParts / kXcds)) % kParts;
         const uint32_t p0 = (uint32_t)(((uint64_t)n_tiles * part) / kParts);
         const uint32_t p1 = (uint32_t)(((uint64_t)n_tiles * (part + 1)) / kParts);
         // a relaxed read first: exhausted partitions cost no atomic
@@ -359,54 +386,55 @@ __global__ __launch_bounds__(kBlock) void k_filter(
           got = true;
           break;
         }
-        part = part + 1 == kParts ? 0 : part + 1;
-        --parts_left;
+        ++visit;
       }
-      if (!got) return;
+      if (!got) break;
     }
     // decode the tile
     const uint32_t b = rfl(tile_block[t]);
-    if (b >= cfg.n_blocks) return;
-    const uint32_t row0 = rfl(blocks[b].row0);
-    const uint32_t row_end = rfl(blocks[b].row_end);
+    if (b >= cfg.n_blocks) break;
+    TileJob job;
+    job.row0 = rfl(blocks[b].row0);
+    job.row_end = min(rfl(blocks[b].row_end), cfg.n_rows);
     const uint32_t cbeg = rfl(blocks[b].col_begin);
     const uint32_t cend = rfl(blocks[b].col_end);
     const uint32_t k = t - rfl(blocks[b].tile_begin);
     const uint32_t task = rfl(blocks[b].task);
     const bool self = rfl(blocks[b].self) != 0;
     const TaskDesc *td = tasks + task;
-    const int32_t *slack = reinterpret_cast<const int32_t *>(tables + rfl(td->slack_off));
-    const uint32_t *cmin = tables + rfl(td->cmin_off);
-    const uint32_t *cmax = tables + rfl(td->cmax_off);
-    const uint32_t *sstart = sstart_cols + rfl64(td->col_sstart_off);
-    const uint32_t col_base = rfl(td->col_base);
-    const bool cosine = rfl(td->sim) == SSJ_SIM_COSINE;
-    const uint32_t tp = rfl(td->p), tq = rfl(td->q);
+    job.slack = reinterpret_cast<const int32_t *>(tables + rfl(td->slack_off));
+    job.cmin = tables + rfl(td->cmin_off);
+    job.cmax = tables + rfl(td->cmax_off);
+    job.sstart = sstart_cols + rfl64(td->col_sstart_off);
+    job.col_base = rfl(td->col_base);
+    job.cosine = rfl(td->sim) == SSJ_SIM_COSINE;
+    job.p = rfl(td->p);
+    job.q = rfl(td->q);
     uint32_t c0, c1;
-    bool diag = false;
+    job.diag = false;
     if (self) {
-      const uint32_t n_int = (row0 - cbeg + cfg.tile_cols - 1) / cfg.tile_cols;
+      const uint32_t n_int = (job.row0 - cbeg + cfg.tile_cols - 1) / cfg.tile_cols;
       if (k < n_int) {
         c0 = cbeg + k * cfg.tile_cols;
-        c1 = min(c0 + cfg.tile_cols, row0);
+        c1 = min(c0 + cfg.tile_cols, job.row0);
       } else {
-        c0 = row0;
+        c0 = job.row0;
         c1 = cend;
-        diag = true;
+        job.diag = true;
       }
     } else {
       c0 = cbeg + k * cfg.tile_cols;
       c1 = min(c0 + cfg.tile_cols, cend);
     }
-    uint32_t first_slab = 0;
+    job.first = 0;
     if (resumed) {
       c0 = col;
-      first_slab = slab;
+      job.first = slab;
     }
     resumed = false;
-    if (!run_tile<W, R, U, COS>(bm_rows, bm_cols, size_rows, size_cols, sstart, col_base, slack, cmin,
-                           cmax, cosine, tp, tq, row0, min(row_end, cfg.n_rows), c0,
-                           min(c1, cfg.n_cols), diag, first_slab, sink)) {
+    job.c0 = c0;
+    job.c1 = min(c1, cfg.n_cols);
+    if (!run(job)) {
       // the queue is full: record where this tile resumes, and stop
       const uint32_t fcol = rfl(sink.fail_col), fslab = rfl(sink.fail_slab);
       if (lane == 0) {
@@ -419,9 +447,312 @@ __global__ __launch_bounds__(kBlock) void k_filter(
         rs.pad = 0;
         if (q < cfg.resume_cap) resume_out[q] = rs;
       }
-      return;
+      break;
     }
   }
+  sink_pad(sink);
+}
+
+__device__ __forceinline__ void sink_init(Sink &sink, uint2 *queue, JoinCounters *ctr,
+                                          const FilterConfig &cfg, uint2 *stage) {
+  sink.queue = queue;
+  sink.ctr = ctr;
+  sink.cap = cfg.cap;
+  sink.chunk = cfg.chunk;
+  sink.pos = 0;
+  sink.end = 0;
+  sink.stage = stage;
+  sink.fill = 0;
+  sink.first_col = 0;
+  sink.first_slab = 0;
+  sink.fail_col = 0;
+  sink.fail_slab = 0;
+}
+
+// Vector-ALU filter for one bitmap width (W words, R rows per lane, U
+// columns per step).
+template <int W, int R, int U, bool COS>
+__global__ __launch_bounds__(kBlock) void k_filter(
+    const uint64_t *__restrict__ bm_rows, const uint64_t *__restrict__ bm_cols,
+    const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
+    const uint32_t *__restrict__ sstart_cols, const uint32_t *__restrict__ tables,
+    const TaskDesc *__restrict__ tasks, const RowBlock *__restrict__ blocks,
+    const uint32_t *__restrict__ tile_block, uint2 *__restrict__ queue,
+    JoinCounters *__restrict__ ctr, const Resume *__restrict__ resume_in,
+    Resume *__restrict__ resume_out, FilterConfig cfg) {
+  __shared__ uint2 stage[kBlock / 64][kStage];
+  Sink sink;
+  sink_init(sink, queue, ctr, cfg, stage[threadIdx.x >> 6]);
+  persistent(tables, tasks, blocks, tile_block, sstart_cols, ctr, resume_in, resume_out, cfg,
+             sink, [&](const TileJob &jb) {
+               return run_tile<W, R, U, COS>(bm_rows, bm_cols, size_rows, size_cols, jb.sstart,
+                                             jb.col_base, jb.slack, jb.cmin, jb.cmax, jb.cosine,
+                                             jb.p, jb.q, jb.row0, jb.row_end, jb.c0, jb.c1,
+                                             jb.diag, jb.first, sink);
+             });
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core filter (b = 64, 128, 256, 512).
+//
+// With every bit of a bitmap mapped to +1 (set) or -1 (clear), the dot
+// product of two such vectors over K bits is K - 2 popcount(b_r xor b_s), so
+// the test of Theorem 1 reads dot >= T = K - 2 slack.  The values +-1 are
+// exact in fp4 (e2m1) and the dot products are small integers, exact in the
+// fp32 accumulator, so the decision is the same as the vector-ALU kernel's.
+// One v_mfma_scale_f32_32x32x64_f8f6f4 scores 32 columns against 32 rows
+// over 64 bits:
+//   - MFMA rows (A) are 32 consecutive columns of the sweep (one step),
+//     loaded per step from the column sign planes, the next step's while
+//     the current one computes;
+//   - MFMA columns (B) are 32 of the wave's rows, RT such row tiles, held in
+//     registers for the whole tile;
+//   - lane l holds row l%32 of every row tile and 16 of the step's columns,
+//     8(v/4) + 4(l/32) + v%4 for v = 0..15.  Steps never cross a size group
+//     (a group's last step is partial; lanes past its end load zeros), so
+//     one threshold per lane and row tile covers all 16 values: the max of
+//     the 16 dot products against T is the whole fast-path test.
+// The slow path stages the kept pairs in a fixed order (row tile, then v,
+// then lane), so a step resumed after a full queue skips exactly the pairs
+// it had written.
+
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef float v16f_t __attribute__((ext_vector_type(16)));
+
+constexpr float kNever = 1.0e30f;  // threshold of a row that no column of the group pairs with
+
+template <int W, int RT>
+struct MRows {
+  uint4 sg[RT][W];  // this lane's half of every 64-bit block of its row in each row tile
+  float thr[RT];    // dot threshold for the current size group
+  uint32_t size[RT];
+  uint32_t cmn[RT];
+  uint32_t cmx[RT];
+  uint32_t idx;     // this lane's row in row tile 0 (row tile rt: idx + 32 rt)
+};
+
+__device__ __forceinline__ v16f_t mfma_pm1(const uint4 &a, const uint4 &b, const v16f_t &c) {
+  const v8i_t x = {(int)a.x, (int)a.y, (int)a.z, (int)a.w, 0, 0, 0, 0};
+  const v8i_t y = {(int)b.x, (int)b.y, (int)b.z, (int)b.w, 0, 0, 0, 0};
+  // formats 4/4: fp4 (e2m1) for A and B; scales 2^0 (e8m0 127)
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, c, 4, 4, 0, 127, 0, 127);
+}
+
+// This lane's half of every block of column `col`, or zeros when !ok: the
+// planes hold n + 1 columns, column n all zero, so every lane loads and no
+// load sits behind a branch.
+template <int W>
+__device__ __forceinline__ void load_signs(const uint4 *__restrict__ planes, uint32_t n,
+                                           uint32_t col, bool ok, uint32_t h, uint4 (&a)[W]) {
+  const size_t c = ok ? col : n;
+#pragma unroll
+  for (int kb = 0; kb < W; ++kb) a[kb] = planes[((size_t)kb * (n + 1) + c) * 2 + h];
+}
+
+// Slow path of one step at columns [j0, j0 + 32) of a group ending at gend:
+// stage the kept pairs in the order (row tile, lane, v).  Only row tiles
+// whose best value reaches their threshold are looked at; in them each lane
+// packs its kept values into the bits of one word, and the wave walks the
+// lanes that kept something and the set bits of each, one pair at a time
+// (survivors are rare, and a fixed order lets a resumed step skip exactly
+// the pairs it had written).  `skip` pairs are dropped first.
+template <int W, int RT, bool DIAG>
+__device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&a)[W],
+                                          const float (&mx)[RT], uint32_t j0, uint32_t gend,
+                                          uint32_t &skip, Sink &sink) {
+  const uint32_t lane = threadIdx.x & 63, h = lane >> 5;
+  const uint32_t cb = j0 + 4u * h;  // this lane's column for v is cb + 8(v/4) + v%4
+  const uint32_t row0 = (uint32_t)__builtin_amdgcn_readlane((int)rw.idx, 0);  // lane 0: row0
+  uint32_t done = 0;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    if (!__ballot(mx[rt] >= rw.thr[rt])) continue;
+    // the step's dot products of this row tile again (the fast path does
+    // not keep them: registers are what limits the waves per SIMD)
+    v16f_t d = {};
+#pragma unroll
+    for (int kb = 0; kb < W; ++kb) d = mfma_pm1(a[kb], rw.sg[rt][kb], d);
+    const uint32_t my_row = rw.idx + 32u * rt;
+    uint32_t k = 0;  // bit v: value v kept (built by shifting: no wide constants)
+#pragma unroll
+    for (int v = 15; v >= 0; --v) {
+      const uint32_t col = cb + 8u * (v / 4) + (uint32_t)(v % 4);
+      bool kp = d[v] >= rw.thr[rt] && col < gend;
+      if (DIAG) kp = kp && col < my_row;
+      k = (k << 1) | (kp ? 1u : 0u);
+    }
+    unsigned long long lm = __ballot(k != 0);
+    while (lm) {
+      const uint32_t L = (uint32_t)__builtin_ctzll(lm);
+      lm &= lm - 1;
+      uint32_t kk = (uint32_t)__builtin_amdgcn_readlane((int)k, (int)L);
+      const uint32_t row = row0 + 32u * rt + (L & 31u);
+      const uint32_t cL = j0 + 4u * (L >> 5);
+      while (kk) {
+        const uint32_t v = (uint32_t)__builtin_ctz(kk);
+        kk &= kk - 1;
+        if (skip) {
+          --skip;
+          ++done;
+          continue;
+        }
+        if (sink.fill == kStage && !flush(sink)) return false;
+        if (sink.fill == 0) {
+          sink.first_col = j0;
+          sink.first_slab = done;
+        }
+        if (lane == 0) sink.stage[sink.fill] = make_uint2(row, cL + 8u * (v >> 2) + (v & 3u));
+        ++sink.fill;
+        ++done;
+      }
+    }
+  }
+  return true;
+}
+
+// One step: columns [j0, j0 + 32) of a group ending at g1 against the
+// wave's rows; the slow path stages the kept pairs.  False when the queue
+// filled.
+template <int W, int RT, bool DIAG>
+__device__ __forceinline__ bool step_mfma(const uint4 (&a)[W], const MRows<W, RT> &rw,
+                                          uint32_t j0, uint32_t g1, uint32_t &skip, Sink &sink) {
+  // Two accumulators: row tile rt's products go into the registers of row
+  // tile rt-2 once those are reduced, so one row tile's MFMA runs while the
+  // previous one is reduced and only 32 registers hold dot products (the
+  // waves per SIMD are bounded by registers).
+  float mx[RT];
+  float best = -kNever;
+  v16f_t acc[2];
+#pragma unroll
+  for (int rt = 0; rt < RT + 2; ++rt) {
+    if (rt >= 2) {
+      const v16f_t &x = acc[rt & 1];
+      // max of the 16 values, as a tree of 3-input maxima
+      float m0 = __builtin_fmaxf(__builtin_fmaxf(x[0], x[1]), x[2]);
+      float m1 = __builtin_fmaxf(__builtin_fmaxf(x[3], x[4]), x[5]);
+      float m2 = __builtin_fmaxf(__builtin_fmaxf(x[6], x[7]), x[8]);
+      float m3 = __builtin_fmaxf(__builtin_fmaxf(x[9], x[10]), x[11]);
+      float m4 = __builtin_fmaxf(__builtin_fmaxf(x[12], x[13]), x[14]);
+      m0 = __builtin_fmaxf(__builtin_fmaxf(m0, m1), m2);
+      m3 = __builtin_fmaxf(__builtin_fmaxf(m3, m4), x[15]);
+      mx[rt - 2] = __builtin_fmaxf(m0, m3);
+      best = __builtin_fmaxf(best, mx[rt - 2] - rw.thr[rt - 2]);
+    }
+    if (rt < RT) {
+      v16f_t t = {};
+#pragma unroll
+      for (int kb = 0; kb < W; ++kb) t = mfma_pm1(a[kb], rw.sg[rt][kb], t);
+      acc[rt & 1] = t;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // the slow path is laid out of line: the fast path falls through
+  if (__builtin_expect(__ballot(best >= 0.f) != 0, 0)) {
+    if (!emit_mfma<W, RT, DIAG>(rw, a, mx, j0, g1, skip, sink)) return false;
+  }
+  skip = 0;
+  return true;
+}
+
+// The steps of columns [j, g1) of one size group.  Column loads run two
+// steps ahead in a ring of three register buffers; the loop is unrolled by
+// three so that the ring turns without register copies (a copy of a buffer
+// still being loaded would wait for that load).
+template <int W, int RT, bool DIAG>
+__device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, uint32_t n_cols,
+                                           const MRows<W, RT> &rw, uint32_t j, uint32_t g1,
+                                           uint32_t &skip, Sink &sink) {
+  const uint32_t lane = threadIdx.x & 63, h = lane >> 5, jr = lane & 31;
+  uint4 b0[W], b1[W], b2[W];
+  load_signs<W>(sg_cols, n_cols, j + jr, j + jr < g1, h, b0);
+  load_signs<W>(sg_cols, n_cols, j + 32 + jr, j + 32 + jr < g1, h, b1);
+  uint32_t j0 = j;
+  for (;;) {
+    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b2);
+    if (!step_mfma<W, RT, DIAG>(b0, rw, j0, g1, skip, sink)) return false;
+    if ((j0 += 32) >= g1) break;
+    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b0);
+    if (!step_mfma<W, RT, DIAG>(b1, rw, j0, g1, skip, sink)) return false;
+    if ((j0 += 32) >= g1) break;
+    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b1);
+    if (!step_mfma<W, RT, DIAG>(b2, rw, j0, g1, skip, sink)) return false;
+    if ((j0 += 32) >= g1) break;
+  }
+  return true;
+}
+
+// One tile on the matrix cores: rows [row0, row_end) (at most 32*RT),
+// columns [c0, c1).
+template <int W, int RT, bool COS>
+__device__ __forceinline__ bool run_tile_mfma(const uint4 *__restrict__ sg_rows,
+                                              const uint4 *__restrict__ sg_cols, uint32_t n_rows,
+                                              uint32_t n_cols, const uint32_t *__restrict__ size_rows,
+                                              const uint32_t *__restrict__ size_cols,
+                                              const TileJob &jb, Sink &sink) {
+  const uint32_t lane = threadIdx.x & 63, h = lane >> 5, jr = lane & 31;
+  constexpr int32_t K = 64 * W;
+  MRows<W, RT> rw;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const uint32_t i = jb.row0 + 32u * rt + jr;
+    if (rt == 0) rw.idx = i;
+    if (i < jb.row_end) {
+      const uint32_t a = size_rows[i];
+      rw.size[rt] = a;
+      rw.cmn[rt] = jb.cmin[a];
+      rw.cmx[rt] = jb.cmax[a];
+    } else {
+      rw.size[rt] = 0;
+      rw.cmn[rt] = 0xFFFFFFFFu;
+      rw.cmx[rt] = 0;
+    }
+    load_signs<W>(sg_rows, n_rows, i, i < jb.row_end, h, rw.sg[rt]);
+  }
+  uint32_t skip = jb.first;
+  uint32_t j = jb.c0;
+  while (j < jb.c1) {
+    const uint32_t c = rfl(size_cols[j]);
+    const uint32_t g1 =
+        min(max(jb.col_base + rfl(jb.sstart[c + 1]), j + 1), jb.c1);  // advances
+    bool any_ok = false;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const bool in_band = c >= rw.cmn[rt] && c <= rw.cmx[rt];
+      int32_t sl = 0;
+      if (in_band) sl = (COS && jb.cosine) ? cosine_slack(rw.size[rt], c, jb.p, jb.q)
+                                           : jb.slack[rw.size[rt] + c];
+      rw.thr[rt] = in_band ? (float)(K - 2 * sl) : kNever;
+      any_ok |= in_band;
+    }
+    if (__ballot(any_ok)) {
+      const bool ok = jb.diag ? sweep_mfma<W, RT, true>(sg_cols, n_cols, rw, j, g1, skip, sink)
+                              : sweep_mfma<W, RT, false>(sg_cols, n_cols, rw, j, g1, skip, sink);
+      if (!ok) return false;
+    }
+    skip = 0;
+    j = g1;
+  }
+  // the tile's staged pairs go out before the next tile
+  return flush(sink);
+}
+
+template <int W, int RT, bool COS>
+__global__ __launch_bounds__(kBlock) void k_filter_mfma(
+    const uint4 *__restrict__ sg_rows, const uint4 *__restrict__ sg_cols,
+    const uint32_t *__restrict__ size_rows, const uint32_t *__restrict__ size_cols,
+    const uint32_t *__restrict__ sstart_cols, const uint32_t *__restrict__ tables,
+    const TaskDesc *__restrict__ tasks, const RowBlock *__restrict__ blocks,
+    const uint32_t *__restrict__ tile_block, uint2 *__restrict__ queue,
+    JoinCounters *__restrict__ ctr, const Resume *__restrict__ resume_in,
+    Resume *__restrict__ resume_out, FilterConfig cfg) {
+  __shared__ uint2 stage[kBlock / 64][kStage];
+  Sink sink;
+  sink_init(sink, queue, ctr, cfg, stage[threadIdx.x >> 6]);
+  persistent(tables, tasks, blocks, tile_block, sstart_cols, ctr, resume_in, resume_out, cfg,
+             sink, [&](const TileJob &jb) {
+               return run_tile_mfma<W, RT, COS>(sg_rows, sg_cols, cfg.n_rows, cfg.n_cols,
+                                                size_rows, size_cols, jb, sink);
+             });
 }
 
 template <int W, int R, int U, bool COS>
@@ -432,7 +763,15 @@ hipError_t launch_shape(dim3 grid, hipStream_t st, const FilterArgs &a) {
   return hipGetLastError();
 }
 
-// Fixed-width kernels: (padded words, rows per lane, columns per step)
+template <int W, int RT, bool COS>
+hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
+  hipLaunchKernelGGL((k_filter_mfma<W, RT, COS>), grid, dim3(kBlock), 0, st, a.sg_rows,
+                     a.sg_cols, a.size_rows, a.size_cols, a.sstart_cols, a.tables, a.tasks,
+                     a.blocks, a.tile_block, a.queue, a.ctr, a.resume_in, a.resume_out, a.cfg);
+  return hipGetLastError();
+}
+
+// Vector-ALU kernels: (padded words, rows per lane, columns per step)
 #define SSJ_FILTER_SHAPES(X) \
   X(1, 4, 4)                 \
   X(2, 2, 4)                 \
@@ -452,6 +791,13 @@ hipError_t launch_shape(dim3 grid, hipStream_t st, const FilterArgs &a) {
   X(48, 1, 1)                \
   X(64, 1, 1)
 
+// Matrix-core kernels: (words, row tiles of 32 per wave)
+#define SSJ_MFMA_SHAPES(X) \
+  X(1, 3)                  \
+  X(2, 3)                  \
+  X(4, 2)                  \
+  X(8, 1)
+
 }  // namespace
 
 uint32_t filter_padded_words(uint32_t words) {
@@ -462,16 +808,24 @@ uint32_t filter_padded_words(uint32_t words) {
   return 0;
 }
 
-FilterShape filter_shape(uint32_t padded_words) {
-  FilterShape s{0, 0, 0};
-#define X(w, r, u)            \
-  if (padded_words == (w)) {  \
-    s.words = (w);            \
-    s.rows = 64 * (r);        \
-    s.batch = 64 * (r) * (u); \
+FilterShape filter_shape(uint32_t padded_words, bool mfma) {
+  FilterShape s{0, 0, false};
+#define X(w, r, u)           \
+  if (padded_words == (w)) { \
+    s.words = (w);           \
+    s.rows = 64 * (r);       \
   }
   SSJ_FILTER_SHAPES(X)
 #undef X
+  if (mfma) {
+#define X(w, rt)                           \
+  if (padded_words == (w)) {               \
+    s.rows = 32 * (rt);                    \
+    s.mfma = true;                         \
+  }
+    SSJ_MFMA_SHAPES(X)
+#undef X
+  }
   return s;
 }
 
@@ -494,6 +848,16 @@ hipError_t launch_filter(uint32_t padded_words, bool cosine, const FilterArgs &a
   const uint64_t waves_per_block = kBlock / 64;
   dim3 grid((unsigned)std::min<uint64_t>((uint64_t)filter_grid_blocks(),
                                          (need + waves_per_block - 1) / waves_per_block));
+  if (a.sg_rows || a.sg_cols) {
+    if (!a.sg_rows || !a.sg_cols) return hipErrorInvalidValue;
+#define X(w, rt)                                                \
+  if (padded_words == (w))                                      \
+    return cosine ? launch_mfma<w, rt, true>(grid, st, a)       \
+                  : launch_mfma<w, rt, false>(grid, st, a);
+    SSJ_MFMA_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+  }
 #define X(w, r, u)                                              \
   if (padded_words == (w))                                      \
     return cosine ? launch_shape<w, r, u, true>(grid, st, a)    \

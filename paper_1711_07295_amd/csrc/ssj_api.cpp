@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -158,6 +159,12 @@ void d2h(T *dst, const T *src, uint64_t n, hipStream_t st) {
   if (n == 0) return;
   check(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
 }
+// The counters the host reads sit before the tile cursors: copy only those.
+template <>
+void d2h<JoinCounters>(JoinCounters *dst, const JoinCounters *src, uint64_t n, hipStream_t st) {
+  if (n != 1) throw Fail{SSJ_E_DEVICE};
+  check(hipMemcpyAsync(dst, src, offsetof(JoinCounters, tile_next), hipMemcpyDeviceToHost, st));
+}
 template <class T>
 void h2d(T *dst, const T *src, uint64_t n, hipStream_t st) {
   if (n == 0) return;
@@ -206,11 +213,18 @@ struct Space {
   uint32_t n_bm = 0;
   uint32_t bm_words[kMaxClasses] = {0, 0, 0, 0};
   uint64_t *bm[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  // sign planes of the bitmaps (matrix-core filter), beside bm[k]
+  uint4 *sg[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
 
   const uint32_t *ss(uint32_t s) const { return sstart_h.data() + (size_t)s * stride; }
   const uint64_t *bitmaps(uint32_t words) const {
     for (uint32_t k = 0; k < n_bm; ++k)
       if (bm_words[k] == words) return bm[k];
+    return nullptr;
+  }
+  const uint4 *signs(uint32_t words) const {
+    for (uint32_t k = 0; k < n_bm; ++k)
+      if (bm_words[k] == words) return sg[k];
     return nullptr;
   }
 };
@@ -308,6 +322,19 @@ void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCoun
   sp.bm_words[sp.n_bm] = words;
   sp.bm[sp.n_bm] = out;
   ++sp.n_bm;
+}
+
+// Sign planes of the space's bitmaps at `words` words (built before).
+void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st) {
+  for (uint32_t k = 0; k < sp.n_bm; ++k) {
+    if (sp.bm_words[k] != words) continue;
+    if (sp.sg[k]) return;
+    uint4 *planes = ar.alloc<uint4>((sp.n + 1) * words * 2);
+    check(launch_expand_signs(sp.bm[k], words, sp.n, planes, st));
+    sp.sg[k] = planes;
+    return;
+  }
+  throw Fail{SSJ_E_DEVICE};
 }
 
 // Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to 8
@@ -579,7 +606,7 @@ struct Plan {
   uint32_t n_tiles = 0;
   uint64_t band_pairs = 0;
   uint64_t filter_ops = 0;       // sum over band pairs of b/16 + 1
-  uint32_t max_batch = 0;        // largest queue reservation of the kernels used
+  bool mfma = true;              // matrix-core filter where it exists (row block height)
   // per width slot: its tiles [tile_lo[k], tile_hi[k]), padded width, work
   uint32_t n_slots = 0;
   uint32_t slot_words[kMaxClasses] = {0, 0, 0, 0};
@@ -636,8 +663,7 @@ void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint
   const uint32_t col_base = (uint32_t)C.h_sides[tk.col_side].base;
   const uint32_t *cmin = pl.tables.data() + td.cmin_off;
   const uint32_t *cmax = pl.tables.data() + td.cmax_off;
-  const FilterShape shape = filter_shape(words);
-  pl.max_batch = std::max(pl.max_batch, shape.batch);
+  const FilterShape shape = filter_shape(words, pl.mfma);
   auto col_lo = [&](uint64_t a) -> uint32_t {  // first column with size >= cmin[a]
     const uint64_t c = cmin[a];
     return c > c_max ? col_n : cs[c];
@@ -753,6 +779,7 @@ struct JoinConfig {
   bool cols_resident = false;  // the column space is an index's
   bool by_col = false;         // tasks are keyed by their column side, and the result pairs
                                // are (column, row): the roles of a swapped R-S join
+  bool mfma = true;            // matrix-core filter at the widths it exists for
 };
 
 // Plans and runs the tasks over prepared spaces R (rows) and C (columns; C
@@ -764,6 +791,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   const bool automatic = jc.b_bits == 0;
   const uint32_t n_tasks = (uint32_t)tasks.size();
   Plan pl;
+  pl.mfma = jc.mfma;
   pl.tasks.resize(n_tasks);
   std::vector<std::vector<WidthClass>> classes(n_tasks);
   std::vector<uint64_t> task_band(n_tasks, 0);
@@ -847,6 +875,22 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   }
   if (!jc.rows_resident) space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st);
   if (!jc.cols_resident) space_bitmaps_multi(C, bw, bb, nbw, ar, ctr, st);
+  // sign planes for the widths the matrix-core kernel runs (an index holds
+  // its own)
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    const uint32_t w = pl.slot_words[k];
+    if (!filter_shape(w, jc.mfma).mfma) continue;
+    if (jc.rows_resident) {
+      if (!R.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
+    } else {
+      space_signs(R, w, ar, st);
+    }
+    if (jc.cols_resident) {
+      if (!C.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
+    } else {
+      space_signs(C, w, ar, st);
+    }
+  }
   if (pl.n_slots == 0) {
     // no bitmaps (every row past the cutoff): check the token order directly
     if (!jc.rows_resident)
@@ -870,7 +914,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
           prev = c.max_size;
         }
       }
-      const uint64_t rows = filter_shape(pl.slot_words[k]).rows;
+      const uint64_t rows = filter_shape(pl.slot_words[k], pl.mfma).rows;
       const uint64_t want = slot_band / (rows * kMinSlotTiles);
       tile_cols = (uint32_t)std::max<uint64_t>(kMinTileCols, std::min<uint64_t>(tile_cols, want));
     }
@@ -967,11 +1011,16 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   check(launch_expand_tiles(d_blocks, (uint32_t)nB, pl.n_tiles, d_tile_block, st));
   check(hipEventRecord(t_prep.ev[1], st));
 
-  // filter / verify rounds.  A queue reservation covers one step of U
-  // columns for all of a wave's rows; the queue must hold the largest such
-  // batch, or a full step could never be written and its tile never resumed.
-  const uint64_t qcap = std::max<uint64_t>(std::max<uint64_t>(pl.max_batch, 4096),
-                                           std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
+  // filter / verify rounds.  A wave reserves queue slots a chunk at a time
+  // and writes staged runs (at most kFilterStage pairs) into its chunk; the
+  // queue must hold at least one chunk, or a run could never be written and
+  // its tile never resumed.  Chunks are small against the queue, so that
+  // many waves hold one in a round (at most 1024 slots each: the unused end
+  // of a chunk costs verification a sentinel read per slot).
+  static_assert(kFilterStage <= 4096, "the queue holds at least 4096 entries");
+  const uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
+  const uint32_t chunk =
+      (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
   uint2 *queue = ar.alloc<uint2>(qcap);
   const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
   Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
@@ -1012,6 +1061,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   cfg.n_blocks = (uint32_t)nB;
   cfg.resume_cap = max_waves;
   cfg.cap = qcap;
+  cfg.chunk = chunk;
   for (;;) {
     if (pl.n_tiles == 0) break;
     cfg.n_resume_in = n_resume_in;
@@ -1024,7 +1074,9 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       cfg.tile_cols = pl.slot_tile_cols[k];
       cfg.cls = k;
       const uint32_t w = pl.slot_words[k];
-      FilterArgs fa{R.bitmaps(w), C.bitmaps(w), R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
+      const bool mf = filter_shape(w, jc.mfma).mfma;
+      FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
+                    mf ? C.signs(w) : nullptr, R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
                     d_blocks, d_tile_block, queue, ctr, res_a, res_b, cfg};
       t_filter.emplace_back();
       t_filter_slot.push_back(k);
@@ -1223,6 +1275,7 @@ JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
   if (opts && opts->queue_capacity) jc.cap = opts->queue_capacity;
   jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
   jc.cutoff = opts && (opts->flags & SSJ_FLAG_CUTOFF);
+  jc.mfma = !(opts && (opts->flags & SSJ_FLAG_VALU));
   return jc;
 }
 
@@ -1503,6 +1556,10 @@ int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *
         for (int k = 0; k < 4; ++k) bits[k] = 64 * kAutoWords[k];
         space_bitmaps_multi(idx->S, kAutoWords, bits, 4, idx->ar, ctr, st);
       }
+      // sign planes of every width the matrix-core filter runs
+      for (uint32_t k = 0; k < idx->S.n_bm; ++k)
+        if (filter_shape(idx->S.bm_words[k], true).mfma)
+          space_signs(idx->S, idx->S.bm_words[k], idx->ar, st);
       d2h(&idx->S.ctr_h, ctr, 1, st);
       sync(st);
       if (idx->S.ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};

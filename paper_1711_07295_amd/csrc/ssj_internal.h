@@ -19,7 +19,8 @@ constexpr uint32_t kMaxWords = 64;
 constexpr int kBlock = 256;
 
 // Partitions of a tile range (one per XCD of the MI355X).
-constexpr uint32_t kParts = 8;
+constexpr uint32_t kXcds = 8;   // XCDs of an MI355X (workgroups go to them round-robin)
+constexpr uint32_t kParts = 64; // tile-cursor partitions per width class, kParts / kXcds per XCD
 // Width classes of one join (one filter launch each).
 constexpr uint32_t kMaxClasses = 4;
 
@@ -33,8 +34,9 @@ struct JoinCounters {
   uint32_t error;                   // validation error bits (kErr*)
   uint32_t max_size;                // largest set size seen
   // Tile cursors: each width class's tile range is cut into kParts
-  // contiguous partitions, one per XCD; each cursor counts the tiles handed
-  // out from its partition.  Each sits in its own 128-byte line.
+  // contiguous partitions, kParts / kXcds per XCD; each cursor counts the
+  // tiles handed out from its partition.  Each sits in its own 128-byte
+  // line.  The host reads only the fields above.
   alignas(128) uint32_t tile_next[kMaxClasses][kParts][32];
 };
 
@@ -112,9 +114,12 @@ struct RowBlock {
   uint32_t pad;
 };
 
-// A tile to resume after a queue drain: tile index, first column, and the
-// first slab of rows (rows r*64 .. r*64+63 of the block) of that column
-// still to be written.
+// A tile to resume after a queue drain: tile index, first column, and
+//  - vector-ALU kernel: the first slab of rows (rows r*64 .. r*64+63 of the
+//    block) of that column still to be written;
+//  - matrix-core kernel: `col` starts a step of 32 columns and `slab` counts
+//    the kept pairs of that step already written (in the step's fixed
+//    emission order).
 struct Resume {
   uint32_t tile;
   uint32_t col;
@@ -135,6 +140,8 @@ struct FilterConfig {
   unsigned long long cap; // survivor queue capacity (entries)
   uint32_t tile_lo;       // this launch's tile range [tile_lo, tile_hi)
   uint32_t tile_hi;
+  uint32_t chunk;         // queue slots a wave reserves at a time (kFilterStage..cap)
+  uint32_t pad;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -212,24 +219,41 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
                                  uint32_t in_words, uint32_t out_words, uint64_t *out,
                                  hipStream_t st);
 
+// Sign planes of bitmaps for the matrix-core filter: bit k of a set's
+// bitmap becomes the fp4 (e2m1) value +1 (0x2) when set and -1 (0xA) when
+// clear.  64-bit block kb of set s is stored as two uint4 halves at
+// planes[(kb * (n + 1) + s) * 2 + h]; half h holds bits 32h..32h+31 of the
+// block, bit 8e+m of a half in nibble m of its dword e.  Set n is all zero
+// (lanes with no set load it).  `bm`: n sets of `words` words, in the
+// order the planes take; planes: (n + 1) * words * 2 entries.
+hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
+                               hipStream_t st);
+
 // tile_block[t] = row block of tile t
 hipError_t launch_expand_tiles(const RowBlock *blocks, uint32_t n_blocks, uint32_t n_tiles,
                                uint32_t *tile_block, hipStream_t st);
 
+// Kept pairs a wave stages in LDS before one queue reservation: the
+// largest reservation a filter launch makes.
+constexpr uint32_t kFilterStage = 256;
+
 // Filter geometry for a padded width.
 struct FilterShape {
   uint32_t words;      // padded 64-bit words per bitmap
-  uint32_t rows;       // rows per wave = 64 * R
-  uint32_t batch;      // most pairs one queue reservation can hold = 64 * R * U
+  uint32_t rows;       // rows per wave: 64 * R (vector ALU) or 32 * RT (matrix cores)
+  bool mfma;           // the matrix-core kernel (sign planes) runs this width
 };
 // Padded word count the filter is instantiated for (>= words), 0 if none.
 uint32_t filter_padded_words(uint32_t words);
-FilterShape filter_shape(uint32_t padded_words);
+// mfma: prefer the matrix-core kernel where it exists for the width
+FilterShape filter_shape(uint32_t padded_words, bool mfma);
 int filter_grid_blocks();
 
 struct FilterArgs {
   const uint64_t *bm_rows;
   const uint64_t *bm_cols;
+  const uint4 *sg_rows;         // sign planes (matrix-core kernel), else null
+  const uint4 *sg_cols;
   const uint32_t *size_rows;
   const uint32_t *size_cols;
   const uint32_t *sstart_cols;  // group-start tables of the column space
@@ -246,7 +270,9 @@ struct FilterArgs {
 
 // One launch for the width padded_words (from filter_padded_words); cosine:
 // some task of the launch uses Cosine (a kernel variant that computes its
-// thresholds per size pair).
+// thresholds per size pair).  With sign planes given, the matrix-core kernel
+// runs (filter_shape(padded_words, true).mfma must hold); else the vector-ALU
+// kernel.  The Resume entries the two write are not interchangeable.
 hipError_t launch_filter(uint32_t padded_words, bool cosine, const FilterArgs &args,
                          hipStream_t st);
 

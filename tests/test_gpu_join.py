@@ -58,7 +58,7 @@ def test_selfjoin_10k_workload():
         assert st["band_pairs"] == oracle.band_pairs(c.sizes(), p, q)
 
 
-@pytest.mark.parametrize("b", [64, 128, 256])
+@pytest.mark.parametrize("b", [64, 128, 192, 256, 512])
 @pytest.mark.parametrize("pq", [(1, 2), (4, 5)])
 def test_survivors_match_oracle(b, pq):
     p, q = pq
