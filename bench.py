@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 PEAK_INT_OPS = 256 * 64 * 2.4e9   # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_FP4 = 10.1e15                # dense fp4 MFMA flop/s (published)
 PEAK_HBM = 8.0e12                 # bytes/s
-MFMA_BITS = (64, 128, 256, 512)   # widths the matrix-core filter runs
+MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
 
 # HBM bytes per launch of the dominant filter launch (the b = 64 class of the
 # 1,000,000-set workload at 4/5), from two rocprofv3 --pmc passes (FETCH_SIZE,
@@ -219,7 +219,7 @@ def roofline_of(stats_list, steps, valu=False):
     """Roofline entry of the dominant filter launch (the width class with the
     most algorithmic work), from the library's per-class event timings.
 
-    Matrix-core kernel (b = 64..512): per band pair the contraction of two
+    Matrix-core kernel (b = 64, 128, 256): per band pair the contraction of two
     +-1 vectors of b entries, 2b fp4 flops, against the dense fp4 peak.
     Vector-ALU kernel: per band pair b/32 xor + b/32 popcount-accumulate + 1
     compare, int32 lane-ops against the vector ALU peak (the library's

@@ -141,7 +141,7 @@ typedef struct {
 #define SSJ_FLAG_CUTOFF 2u
 
 /* Run the bitmap filter on the vector ALUs at every width.  By default the
- * widths b = 64, 128, 256 and 512 run on the matrix cores, which score the
+ * widths b = 64, 128 and 256 run on the matrix cores, which score the
  * Hamming distance of Theorem 1 as a dot product of +-1 vectors (exact);
  * the two kernels keep the same pairs.  Changes the work, never the
  * result. */

@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-core filter (b = 64, 128, 256, 512).
+// Matrix-core filter (b = 64, 128, 256).
 //
 // With every bit of a bitmap mapped to +1 (set) or -1 (clear), the dot
 // product of two such vectors over K bits is K - 2 popcount(b_r xor b_s), so
@@ -549,17 +549,51 @@ __device__ __forceinline__ void load_signs(const uint4 *__restrict__ planes, uin
   for (int kb = 0; kb < W; ++kb) a[kb] = planes[((size_t)kb * (n + 1) + c) * 2 + h];
 }
 
+// Stage one ballot mask of kept pairs (row `row` of the lanes' row tile is
+// the caller's; column per lane): `skip` pairs are dropped first, `done`
+// counts the step's pairs in order.
+__device__ __forceinline__ bool stage_mask(unsigned long long m, uint32_t row, uint32_t col,
+                                           uint32_t j0, uint32_t &skip, uint32_t &done,
+                                           Sink &sink) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t cnt = (uint32_t)__popcll(m);
+  if (skip) {
+    if (skip >= cnt) {
+      skip -= cnt;
+      done += cnt;
+      return true;
+    }
+    for (uint32_t x = 0; x < skip; ++x) m &= m - 1;  // drop the lowest `skip` lanes
+    done += skip;
+    cnt -= skip;
+    skip = 0;
+  }
+  if (sink.fill + cnt > kStage && !flush(sink)) return false;
+  if (sink.fill == 0) {
+    sink.first_col = j0;
+    sink.first_slab = done;
+  }
+  if ((m >> lane) & 1ull)
+    sink.stage[sink.fill + (uint32_t)__popcll(m & __lanemask_lt())] = make_uint2(row, col);
+  sink.fill += cnt;
+  done += cnt;
+  return true;
+}
+
 // Slow path of one step at columns [j0, j0 + 32) of a group ending at gend:
-// stage the kept pairs in the order (row tile, lane, v).  Only row tiles
-// whose best value reaches their threshold are looked at; in them each lane
-// packs its kept values into the bits of one word, and the wave walks the
-// lanes that kept something and the set bits of each, one pair at a time
-// (survivors are rare, and a fixed order lets a resumed step skip exactly
-// the pairs it had written).  `skip` pairs are dropped first.
+// stage the kept pairs.  Only row tiles whose best value reaches their
+// threshold are looked at; in them each lane packs its kept values into the
+// bits of one word.  Few lanes with kept values (the usual case): the wave
+// walks those lanes and their set bits, one pair at a time, in the order
+// (lane, v).  Many: one ballot per value v stages whole masks, in the order
+// (v, lane).  The choice depends only on the step's values, so a step
+// resumed after a full queue takes the same order and skips exactly the
+// `skip` pairs it had written.
 template <int W, int RT, bool DIAG>
 __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&a)[W],
                                           const float (&mx)[RT], uint32_t j0, uint32_t gend,
                                           uint32_t &skip, Sink &sink) {
+  constexpr uint32_t kFewLanes = 4;
   const uint32_t lane = threadIdx.x & 63, h = lane >> 5;
   const uint32_t cb = j0 + 4u * h;  // this lane's column for v is cb + 8(v/4) + v%4
   const uint32_t row0 = (uint32_t)__builtin_amdgcn_readlane((int)rw.idx, 0);  // lane 0: row0
@@ -582,6 +616,15 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
       k = (k << 1) | (kp ? 1u : 0u);
     }
     unsigned long long lm = __ballot(k != 0);
+    if ((uint32_t)__popcll(lm) > kFewLanes) {
+#pragma unroll 1
+      for (uint32_t v = 0; v < 16; ++v) {
+        const unsigned long long m = __ballot((k >> v) & 1u);
+        if (m && !stage_mask(m, my_row, cb + 8u * (v >> 2) + (v & 3u), j0, skip, done, sink))
+          return false;
+      }
+      continue;
+    }
     while (lm) {
       const uint32_t L = (uint32_t)__builtin_ctzll(lm);
       lm &= lm - 1;
@@ -792,11 +835,13 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
   X(64, 1, 1)
 
 // Matrix-core kernels: (words, row tiles of 32 per wave)
+// (b = 512 stays on the vector ALUs: with eight 64-bit blocks per column a
+// step streams 8 bytes of column planes per pair at the row-tile counts the
+// registers allow, more than L2 delivers; the vector-ALU kernel is faster.)
 #define SSJ_MFMA_SHAPES(X) \
-  X(1, 3)                  \
+  X(1, 4)                  \
   X(2, 3)                  \
-  X(4, 2)                  \
-  X(8, 1)
+  X(4, 3)
 
 }  // namespace
 

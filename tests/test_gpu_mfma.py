@@ -1,4 +1,4 @@
-"""The matrix-core filter (b = 64, 128, 256, 512) against the oracle and the
+"""The matrix-core filter (b = 64, 128, 256) against the oracle and the
 vector-ALU kernel (SSJ_FLAG_VALU).  The matrix cores score the Hamming
 distance of Theorem 1 as a dot product of +-1 vectors, exact in fp32, so
 both kernels must keep exactly the same pairs: the survivor sets
