@@ -145,23 +145,32 @@ __device__ __forceinline__ uint32_t biased_distance(const Rows<W, R> &rw, const 
 template <int W, int R, int U>
 __device__ __forceinline__ bool emit(const Rows<W, R> &rw, const uint32_t (&d)[U][R], uint32_t j,
                                      Sink &sink) {
+  static_assert(U * R <= 32, "one word holds the step's kept flags");
   const unsigned long long below = __lanemask_lt();
+  // bit u*R + r: this lane's pair (column j + u, row slab r) is kept; one
+  // loop then stages the masks, so the staging code exists once
+  uint32_t kb = 0;
 #pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool kp = (int32_t)d[u][r] < 0;
-      const unsigned long long m = __ballot(kp);
-      if (!m) continue;
-      const uint32_t cnt = (uint32_t)__popcll(m);
-      if (sink.fill + cnt > kStage && !flush(sink)) return false;
-      if (sink.fill == 0) {
-        sink.first_col = j + u;
-        sink.first_slab = r;
-      }
-      if (kp) sink.stage[sink.fill + (uint32_t)__popcll(m & below)] = make_uint2(rw.idx[r], j + u);
-      sink.fill += cnt;
+  for (int x = U * R - 1; x >= 0; --x)
+    kb = (kb << 1) | ((int32_t)d[x / R][x % R] < 0 ? 1u : 0u);
+  const uint32_t row_slab0 = rw.idx[0];  // this lane's row in slab r: + 64 r
+#pragma unroll 1
+  for (uint32_t x = 0; x < (uint32_t)(U * R); ++x) {
+    const bool kp = (kb >> x) & 1u;
+    const unsigned long long m = __ballot(kp);
+    if (!m) continue;
+    const uint32_t u = x / R, r = x - u * R;
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    if (sink.fill + cnt > kStage && !flush(sink)) return false;
+    if (sink.fill == 0) {
+      sink.first_col = j + u;
+      sink.first_slab = r;
     }
+    if (kp)
+      sink.stage[sink.fill + (uint32_t)__popcll(m & below)] =
+          make_uint2(row_slab0 + 64u * r, j + u);
+    sink.fill += cnt;
+  }
   return true;
 }
 
@@ -589,10 +598,10 @@ __device__ __forceinline__ bool stage_mask(unsigned long long m, uint32_t row, u
 // (v, lane).  The choice depends only on the step's values, so a step
 // resumed after a full queue takes the same order and skips exactly the
 // `skip` pairs it had written.
-template <int W, int RT, bool DIAG>
+template <int W, int RT>
 __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&a)[W],
                                           const float (&mx)[RT], uint32_t j0, uint32_t gend,
-                                          uint32_t &skip, Sink &sink) {
+                                          bool diag, uint32_t &skip, Sink &sink) {
   constexpr uint32_t kFewLanes = 4;
   const uint32_t lane = threadIdx.x & 63, h = lane >> 5;
   const uint32_t cb = j0 + 4u * h;  // this lane's column for v is cb + 8(v/4) + v%4
@@ -611,8 +620,7 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
 #pragma unroll
     for (int v = 15; v >= 0; --v) {
       const uint32_t col = cb + 8u * (v / 4) + (uint32_t)(v % 4);
-      bool kp = d[v] >= rw.thr[rt] && col < gend;
-      if (DIAG) kp = kp && col < my_row;
+      const bool kp = d[v] >= rw.thr[rt] && col < gend && (!diag || col < my_row);
       k = (k << 1) | (kp ? 1u : 0u);
     }
     unsigned long long lm = __ballot(k != 0);
@@ -653,17 +661,16 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
   return true;
 }
 
-// One step: columns [j0, j0 + 32) of a group ending at g1 against the
-// wave's rows; the slow path stages the kept pairs.  False when the queue
-// filled.
-template <int W, int RT, bool DIAG>
-__device__ __forceinline__ bool step_mfma(const uint4 (&a)[W], const MRows<W, RT> &rw,
-                                          uint32_t j0, uint32_t g1, uint32_t &skip, Sink &sink) {
+// Fast path of one step: columns [j0, j0 + 32) against the wave's rows.
+// Leaves each row tile's best value in mx and returns whether some value
+// reaches its threshold.
+template <int W, int RT>
+__device__ __forceinline__ bool fast_mfma(const uint4 (&a)[W], const MRows<W, RT> &rw,
+                                          float (&mx)[RT]) {
   // Two accumulators: row tile rt's products go into the registers of row
   // tile rt-2 once those are reduced, so one row tile's MFMA runs while the
-  // previous one is reduced and only 32 registers hold dot products (the
+  // previous one is reduced and fewer registers hold dot products (the
   // waves per SIMD are bounded by registers).
-  float mx[RT];
   float best = -kNever;
   v16f_t acc[2];
 #pragma unroll
@@ -689,39 +696,64 @@ __device__ __forceinline__ bool step_mfma(const uint4 (&a)[W], const MRows<W, RT
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  // the slow path is laid out of line: the fast path falls through
-  if (__builtin_expect(__ballot(best >= 0.f) != 0, 0)) {
-    if (!emit_mfma<W, RT, DIAG>(rw, a, mx, j0, g1, skip, sink)) return false;
-  }
-  skip = 0;
-  return true;
+  return __ballot(best >= 0.f) != 0;
 }
 
 // The steps of columns [j, g1) of one size group.  Column loads run two
 // steps ahead in a ring of three register buffers; the loop is unrolled by
 // three so that the ring turns without register copies (a copy of a buffer
-// still being loaded would wait for that load).
-template <int W, int RT, bool DIAG>
+// still being loaded would wait for that load).  The three steps share one
+// slow path, laid out once: a step that keeps something copies its own
+// buffer (loaded by then) and jumps there, and the slow path returns to
+// the step after it.  Instruction cache: the kernel stays small.
+template <int W, int RT>
 __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, uint32_t n_cols,
                                            const MRows<W, RT> &rw, uint32_t j, uint32_t g1,
-                                           uint32_t &skip, Sink &sink) {
+                                           bool diag, uint32_t &skip, Sink &sink) {
   const uint32_t lane = threadIdx.x & 63, h = lane >> 5, jr = lane & 31;
-  uint4 b0[W], b1[W], b2[W];
+  uint4 b0[W], b1[W], b2[W], cur[W];
+  float mx[RT];
+  int phase = 0;
   load_signs<W>(sg_cols, n_cols, j + jr, j + jr < g1, h, b0);
   load_signs<W>(sg_cols, n_cols, j + 32 + jr, j + 32 + jr < g1, h, b1);
   uint32_t j0 = j;
-  for (;;) {
-    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b2);
-    if (!step_mfma<W, RT, DIAG>(b0, rw, j0, g1, skip, sink)) return false;
-    if ((j0 += 32) >= g1) break;
-    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b0);
-    if (!step_mfma<W, RT, DIAG>(b1, rw, j0, g1, skip, sink)) return false;
-    if ((j0 += 32) >= g1) break;
-    load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b1);
-    if (!step_mfma<W, RT, DIAG>(b2, rw, j0, g1, skip, sink)) return false;
-    if ((j0 += 32) >= g1) break;
+step0:
+  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b2);
+  if (__builtin_expect(fast_mfma<W, RT>(b0, rw, mx), 0)) {
+#pragma unroll
+    for (int kb = 0; kb < W; ++kb) cur[kb] = b0[kb];
+    phase = 0;
+    goto slow;
   }
-  return true;
+after0:
+  skip = 0;
+  if ((j0 += 32) >= g1) return true;
+  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b0);
+  if (__builtin_expect(fast_mfma<W, RT>(b1, rw, mx), 0)) {
+#pragma unroll
+    for (int kb = 0; kb < W; ++kb) cur[kb] = b1[kb];
+    phase = 1;
+    goto slow;
+  }
+after1:
+  skip = 0;
+  if ((j0 += 32) >= g1) return true;
+  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b1);
+  if (__builtin_expect(fast_mfma<W, RT>(b2, rw, mx), 0)) {
+#pragma unroll
+    for (int kb = 0; kb < W; ++kb) cur[kb] = b2[kb];
+    phase = 2;
+    goto slow;
+  }
+after2:
+  skip = 0;
+  if ((j0 += 32) >= g1) return true;
+  goto step0;
+slow:
+  if (!emit_mfma<W, RT>(rw, cur, mx, j0, g1, diag, skip, sink)) return false;
+  if (phase == 0) goto after0;
+  if (phase == 1) goto after1;
+  goto after2;
 }
 
 // One tile on the matrix cores: rows [row0, row_end) (at most 32*RT),
@@ -768,9 +800,7 @@ __device__ __forceinline__ bool run_tile_mfma(const uint4 *__restrict__ sg_rows,
       any_ok |= in_band;
     }
     if (__ballot(any_ok)) {
-      const bool ok = jb.diag ? sweep_mfma<W, RT, true>(sg_cols, n_cols, rw, j, g1, skip, sink)
-                              : sweep_mfma<W, RT, false>(sg_cols, n_cols, rw, j, g1, skip, sink);
-      if (!ok) return false;
+      if (!sweep_mfma<W, RT>(sg_cols, n_cols, rw, j, g1, jb.diag, skip, sink)) return false;
     }
     skip = 0;
     j = g1;
