@@ -367,31 +367,38 @@ __device__ __forceinline__ void persistent(const uint32_t *__restrict__ tables,
   }
   const uint32_t n_tiles = cfg.tile_hi - cfg.tile_lo;
   uint32_t *cursors = &ctr->tile_next[cfg.cls][0][0];
-  // The tile range is cut into kParts partitions with a cursor each, so that
-  // the cursors' atomics spread over many addresses.  Workgroups are
-  // dispatched to the XCDs round-robin: a workgroup starts in a partition of
-  // its own XCD (p mod kXcds), takes that XCD's other partitions next, and
-  // only then the rest.
-  const uint32_t base_part = blockIdx.x % kParts;
+  // Each XCD owns one contiguous region of the tile range, so that its
+  // waves sweep neighbouring row blocks whose columns stay in its L2.
+  // Inside a region the tiles are dealt to kSub sub-cursors in blocks of
+  // kDeal, so that the cursors' atomics spread over kSub addresses (atomics
+  // on one address from every XCD serialise) while the region is still
+  // swept as one front.  Workgroups are dispatched to the XCDs round-robin:
+  // a workgroup starts on its own XCD's region, takes that region's other
+  // sub-cursors when its own runs dry, and then the other regions.
+  constexpr uint32_t kSub = kParts / kXcds, kDeal = 4;
+  const uint32_t xcd0 = blockIdx.x % kXcds, sub0 = (blockIdx.x / kXcds) % kSub;
   uint32_t visit = 0;
   for (;;) {
     if (!resumed) {
       if (__hip_atomic_load(&ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       bool got = false;
       while (visit < kParts) {
-        const uint32_t part =
-            (base_part + kXcds * (visit % (kParts / kXcds)) + visit / (kParts / kXcds)) % kParts;
-        const uint32_t p0 = (uint32_t)(((uint64_t)n_tiles * part) / kParts);
-        const uint32_t p1 = (uint32_t)(((uint64_t)n_tiles * (part + 1)) / kParts);
-        // a relaxed read first: exhausted partitions cost no atomic
-        uint32_t tt = p1 - p0;
+        const uint32_t x = (xcd0 + visit / kSub) % kXcds, k = (sub0 + visit) % kSub;
+        const uint32_t r0 = (uint32_t)(((uint64_t)n_tiles * x) / kXcds);
+        const uint32_t len = (uint32_t)(((uint64_t)n_tiles * (x + 1)) / kXcds) - r0;
+        // tiles of the region sub-cursor k owns: blocks k, k + kSub, ...
+        const uint32_t rounds = len / (kSub * kDeal), rem = len - rounds * kSub * kDeal;
+        const uint32_t owned =
+            rounds * kDeal + min(kDeal, rem > k * kDeal ? rem - k * kDeal : 0u);
+        uint32_t *cur = &cursors[(x * kSub + k) * 32];
+        // a relaxed read first: exhausted sub-cursors cost no atomic
+        uint32_t c = owned;
         if (lane == 0 &&
-            __hip_atomic_load(&cursors[part * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                p1 - p0)
-          tt = atomicAdd(&cursors[part * 32], 1u);
-        tt = rfl(tt);
-        if (tt < p1 - p0) {
-          t = cfg.tile_lo + p0 + tt;
+            __hip_atomic_load(cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < owned)
+          c = atomicAdd(cur, 1u);
+        c = rfl(c);
+        if (c < owned) {
+          t = cfg.tile_lo + r0 + ((c / kDeal) * kSub + k) * kDeal + c % kDeal;
           got = true;
           break;
         }

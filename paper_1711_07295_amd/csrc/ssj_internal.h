@@ -20,7 +20,7 @@ constexpr int kBlock = 256;
 
 // Partitions of a tile range (one per XCD of the MI355X).
 constexpr uint32_t kXcds = 8;   // XCDs of an MI355X (workgroups go to them round-robin)
-constexpr uint32_t kParts = 64; // tile-cursor partitions per width class, kParts / kXcds per XCD
+constexpr uint32_t kParts = 64; // tile cursors per width class, kParts / kXcds per XCD
 // Width classes of one join (one filter launch each).
 constexpr uint32_t kMaxClasses = 4;
 
@@ -33,10 +33,11 @@ struct JoinCounters {
   uint32_t n_resume;                // resume entries written this launch
   uint32_t error;                   // validation error bits (kErr*)
   uint32_t max_size;                // largest set size seen
-  // Tile cursors: each width class's tile range is cut into kParts
-  // contiguous partitions, kParts / kXcds per XCD; each cursor counts the
-  // tiles handed out from its partition.  Each sits in its own 128-byte
-  // line.  The host reads only the fields above.
+  // Tile cursors: each width class's tile range is cut into kXcds
+  // contiguous regions, one per XCD, and each region's tiles are dealt to
+  // kParts / kXcds sub-cursors; a cursor counts the tiles it has handed
+  // out.  Each sits in its own 128-byte line.  The host reads only the
+  // fields above.
   alignas(128) uint32_t tile_next[kMaxClasses][kParts][32];
 };
 
