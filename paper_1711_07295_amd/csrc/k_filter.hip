@@ -474,7 +474,7 @@ __device__ __forceinline__ void sink_init(Sink &sink, uint2 *queue, JoinCounters
   sink.queue = queue;
   sink.ctr = ctr;
   sink.cap = cfg.cap;
-  sink.chunk = cfg.chunk;
+  sink.chunk = max(cfg.chunk, kStage);
   sink.pos = 0;
   sink.end = 0;
   sink.stage = stage;
@@ -857,10 +857,10 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
   X(2, 2, 4)                 \
   X(3, 2, 2)                 \
   X(4, 2, 2)                 \
-  X(5, 1, 2)                 \
-  X(6, 1, 2)                 \
-  X(7, 1, 2)                 \
-  X(8, 1, 2)                 \
+  X(5, 1, 1)                 \
+  X(6, 1, 1)                 \
+  X(7, 1, 1)                 \
+  X(8, 1, 1)                 \
   X(10, 1, 1)                \
   X(12, 1, 1)                \
   X(16, 1, 1)                \
