@@ -256,6 +256,42 @@ __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restr
   planes[((uint64_t)kb * (n + 1) + s) * 2 + h] = out;
 }
 
+// Wide Bitmap-Xor bitmaps of the sets in the wide ranges: one wave per set,
+// built in LDS (4096 bits per wave) and written out whole.
+__global__ __launch_bounds__(kBlock) void k_build_wide(const SideDesc *__restrict__ sides,
+                                                        const uint32_t *__restrict__ perm,
+                                                        const WideRange *__restrict__ ranges,
+                                                        uint32_t n_ranges, uint64_t total,
+                                                        uint64_t *__restrict__ out) {
+  __shared__ uint32_t acc[kWavesPerBlock][kWideWords * 2];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t w = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+  if (w >= total) return;
+  uint32_t *a = acc[wv];
+  for (uint32_t x = lane; x < kWideWords * 2; x += 64) a[x] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  // the last range whose first slot is <= w
+  uint32_t lo = 0, hi = n_ranges;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (ranges[mid].slot <= w) lo = mid;
+    else hi = mid;
+  }
+  const WideRange r = ranges[lo];
+  const uint64_t g = r.lo + (w - r.slot);
+  const SideDesc sd = sides[r.side];
+  const uint32_t x = perm[g];
+  const uint64_t o0 = sd.offsets[x], o1 = sd.offsets[x + 1];
+  for (uint64_t t = o0 + lane; t < o1; t += 64) {
+    const uint32_t bit = sd.tokens[t] & (kWideWords * 64 - 1);
+    atomicXor(&a[bit >> 5], 1u << (bit & 31));
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint64_t *dst = out + w * kWideWords;
+  for (uint32_t k = lane; k < kWideWords; k += 64)
+    dst[k] = (uint64_t)a[2 * k] | ((uint64_t)a[2 * k + 1] << 32);
+}
+
 }  // namespace
 
 uint32_t bitmap_seg_blocks(uint64_t n) { return (uint32_t)((n + kSegSets - 1) / kSegSets); }
@@ -318,6 +354,17 @@ hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, u
   const uint64_t total = (n + 1) * words * 2;
   hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, st, bm, words, n, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_wide(const SideDesc *sides, const uint32_t *perm,
+                             const WideRange *ranges, uint32_t n_ranges, uint64_t total,
+                             uint64_t *out, hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  if (n_ranges == 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((total + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL(k_build_wide, grid, dim3(kBlock), 0, st, sides, perm, ranges, n_ranges,
+                     total, out);
   return hipGetLastError();
 }
 

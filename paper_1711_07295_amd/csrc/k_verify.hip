@@ -15,7 +15,9 @@
 // Before the merge, a survivor can be tested once more with wider bitmaps
 // of both sets (the cascade width, the widest a call has built): the bound
 // of Theorem 1 holds at any width, and a wider one prunes most of the false
-// survivors of a narrow class for a few dozen operations.
+// survivors of a narrow class for a few dozen operations.  Pairs of sets too
+// large for that width (its bits saturate) are tested again at the wide
+// width, 4096 bits, when both sets have wide bitmaps.
 //
 // Grid-stride over the queue, one survivor per lane; results are appended
 // with one atomic per wave (ballot + lane rank).
@@ -96,9 +98,10 @@ __global__ __launch_bounds__(kBlock) void k_verify(
       const uint2 qe = queue[e];
       if (qe.x < rows.n && qe.y < cols.n) {
         ++surv;
-        const SideDesc dr = rows.sides[rows.side_of[qe.x]];
-        const SideDesc dc = cols.sides[cols.side_of[qe.y]];
-        const uint32_t task = by_col ? side_task[cols.side_of[qe.y]] : side_task[rows.side_of[qe.x]];
+        const uint32_t sr = rows.side_of[qe.x], sc = cols.side_of[qe.y];
+        const SideDesc dr = rows.sides[sr];
+        const SideDesc dc = cols.sides[sc];
+        const uint32_t task = by_col ? side_task[sc] : side_task[sr];
         const uint32_t x = rows.perm[qe.x], y = cols.perm[qe.y];
         const uint64_t r0 = dr.offsets[x], r1 = dr.offsets[x + 1];
         const uint64_t s0 = dc.offsets[y], s1 = dc.offsets[y + 1];
@@ -118,6 +121,24 @@ __global__ __launch_bounds__(kBlock) void k_verify(
             uint32_t h = 0;
             for (uint32_t w = 0; w < w2; ++w) h += (uint32_t)__popcll(bx[w] ^ by[w]);
             pass = (int64_t)h <= (int64_t)a + c - 2 * (int64_t)need;
+          }
+          // and at the wide width when both sets have wide bitmaps (sets too
+          // large for the cascade width, whose bits saturate)
+          if (pass && rows.bmw) {
+            const uint32_t lr = rows.wide_lo[sr], lc = cols.wide_lo[sc];
+            if (qe.x >= lr && qe.y >= lc) {
+              const uint4 *bx = reinterpret_cast<const uint4 *>(
+                  rows.bmw + (size_t)(rows.wide_slot[sr] + (qe.x - lr)) * kWideWords);
+              const uint4 *by = reinterpret_cast<const uint4 *>(
+                  cols.bmw + (size_t)(cols.wide_slot[sc] + (qe.y - lc)) * kWideWords);
+              uint32_t h = 0;
+              for (uint32_t w = 0; w < kWideWords / 2; ++w) {
+                const uint4 p = bx[w], q = by[w];
+                h += (uint32_t)__popc(p.x ^ q.x) + (uint32_t)__popc(p.y ^ q.y) +
+                     (uint32_t)__popc(p.z ^ q.z) + (uint32_t)__popc(p.w ^ q.w);
+              }
+              pass = (int64_t)h <= (int64_t)a + c - 2 * (int64_t)need;
+            }
           }
           hit = a != 0 && c != 0 && pass &&
                 overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
@@ -182,6 +203,7 @@ hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace
                          unsigned long long results_cap, JoinCounters *ctr, hipStream_t st) {
   if ((rows.bm2 == nullptr) != (cols.bm2 == nullptr) || (rows.bm2 && !w2))
     return hipErrorInvalidValue;
+  if ((rows.bmw == nullptr) != (cols.bmw == nullptr)) return hipErrorInvalidValue;
   dim3 grid(filter_grid_blocks());
   hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
                      tasks, tables, ib, jb, survivors_only, w2, by_col, results, results_cap,

@@ -31,7 +31,7 @@
 namespace ssj {
 namespace {
 
-constexpr uint64_t kDefaultQueue = 1ull << 27;   // 1 GiB of (row, column) pairs
+constexpr uint64_t kDefaultQueue = 1ull << 29;   // 4 GiB of (row, column) pairs
 constexpr uint32_t kDefaultTileCols = 2048;
 // A width class with fewer than about kMinSlotTiles tiles of the default
 // width gets narrower tiles, down to kMinTileCols columns.
@@ -215,6 +215,10 @@ struct Space {
   uint64_t *bm[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
   // sign planes of the bitmaps (matrix-core filter), beside bm[k]
   uint4 *sg[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  // wide bitmaps of the sets larger than kWideMin (verification)
+  bool wide_built = false;
+  uint64_t *bmw = nullptr;
+  uint32_t *wide_lo = nullptr, *wide_slot = nullptr;  // per side
 
   const uint32_t *ss(uint32_t s) const { return sstart_h.data() + (size_t)s * stride; }
   const uint64_t *bitmaps(uint32_t words) const {
@@ -335,6 +339,43 @@ void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st) {
     return;
   }
   throw Fail{SSJ_E_DEVICE};
+}
+
+// Wide bitmaps of every set larger than kWideMin: in size order they are a
+// suffix of each side (from its group start at kWideMin + 1).
+void space_wide(Space &sp, Arena &ar, hipStream_t st) {
+  if (sp.wide_built) return;
+  sp.wide_built = true;
+  std::vector<uint32_t> lo(sp.n_sides, 0xFFFFFFFFu), slot(sp.n_sides, 0);
+  std::vector<WideRange> ranges;
+  uint64_t total = 0;
+  if ((uint64_t)kWideMin + 1 <= (uint64_t)sp.max_size) {
+    for (uint32_t s = 0; s < sp.n_sides; ++s) {
+      const SideDesc &d = sp.h_sides[s];
+      const uint32_t first = sp.ss(s)[kWideMin + 1];
+      if (first >= d.n) continue;
+      WideRange r{};
+      r.lo = (uint32_t)d.base + first;
+      r.hi = (uint32_t)d.base + d.n;
+      r.slot = (uint32_t)total;
+      r.side = s;
+      lo[s] = r.lo;
+      slot[s] = r.slot;
+      total += r.hi - r.lo;
+      if (total >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
+      ranges.push_back(r);
+    }
+  }
+  if (total == 0) return;
+  sp.wide_lo = ar.alloc<uint32_t>(2 * (uint64_t)sp.n_sides);
+  sp.wide_slot = sp.wide_lo + sp.n_sides;
+  h2d(sp.wide_lo, lo.data(), sp.n_sides, st);
+  h2d(sp.wide_slot, slot.data(), sp.n_sides, st);
+  WideRange *d_ranges = ar.alloc<WideRange>(ranges.size());
+  h2d(d_ranges, ranges.data(), ranges.size(), st);
+  sp.bmw = ar.alloc<uint64_t>(total * kWideWords);
+  check(launch_build_wide(sp.d_sides, sp.perm, d_ranges, (uint32_t)ranges.size(), total, sp.bmw,
+                          st));
 }
 
 // Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to 8
@@ -1040,10 +1081,17 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   for (uint32_t k = 0; k < R.n_bm; ++k)
     if (R.bm_words[k] > w2 && C.bitmaps(R.bm_words[k])) w2 = R.bm_words[k];
   const bool cascade = automatic && !jc.survivors_only && pl.n_slots > 0 && w2 > pl.slot_words[0];
+  // wide bitmaps for pairs of large sets (automatic mode, as the cascade);
+  // an index holds its own
+  if (cascade) {
+    if (!jc.rows_resident) space_wide(R, ar, st);
+    if (!jc.cols_resident) space_wide(C, ar, st);
+  }
+  const bool wide = cascade && R.bmw && C.bmw;
   const VerifySpace vrows{R.d_sides, R.side_of, R.perm, cascade ? R.bitmaps(w2) : nullptr,
-                          (uint32_t)R.n};
+                          (uint32_t)R.n, wide ? R.bmw : nullptr, R.wide_lo, R.wide_slot};
   const VerifySpace vcols{C.d_sides, C.side_of, C.perm, cascade ? C.bitmaps(w2) : nullptr,
-                          (uint32_t)C.n};
+                          (uint32_t)C.n, wide ? C.bmw : nullptr, C.wide_lo, C.wide_slot};
   if (!cascade) w2 = 0;
 
   std::deque<Timer> t_filter, t_verify;  // events must not move
@@ -1556,10 +1604,12 @@ int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *
         for (int k = 0; k < 4; ++k) bits[k] = 64 * kAutoWords[k];
         space_bitmaps_multi(idx->S, kAutoWords, bits, 4, idx->ar, ctr, st);
       }
-      // sign planes of every width the matrix-core filter runs
+      // sign planes of every width the matrix-core filter runs, and wide
+      // bitmaps of its large sets for verification
       for (uint32_t k = 0; k < idx->S.n_bm; ++k)
         if (filter_shape(idx->S.bm_words[k], true).mfma)
           space_signs(idx->S, idx->S.bm_words[k], idx->ar, st);
+      space_wide(idx->S, idx->ar, st);
       d2h(&idx->S.ctr_h, ctr, 1, st);
       sync(st);
       if (idx->S.ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};

@@ -230,6 +230,23 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
 hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
                                hipStream_t st);
 
+// Wide bitmaps for verification: Bitmap-Xor at 64 * kWideWords bits of the
+// sets larger than kWideMin (where the widest automatic width no longer
+// prunes: its bits saturate).  In size order those sets are a suffix of each
+// side; WideRange r maps global positions [lo, hi) of side `side` to slots
+// slot + (g - lo) of the wide array.
+constexpr uint32_t kWideWords = 64;
+constexpr uint32_t kWideMin = 256;
+struct WideRange {
+  uint32_t lo, hi, slot, side;
+};
+// out[slot * kWideWords ...] for every slot in [0, total); ranges sorted by
+// slot, n_ranges >= 1 when total > 0.  perm: size-order position -> caller
+// index within its side.
+hipError_t launch_build_wide(const SideDesc *sides, const uint32_t *perm,
+                             const WideRange *ranges, uint32_t n_ranges, uint64_t total,
+                             uint64_t *out, hipStream_t st);
+
 // tile_block[t] = row block of tile t
 hipError_t launch_expand_tiles(const RowBlock *blocks, uint32_t n_blocks, uint32_t n_tiles,
                                uint32_t *tile_block, hipStream_t st);
@@ -284,6 +301,9 @@ struct VerifySpace {
   const uint32_t *perm;
   const uint64_t *bm2;     // size-order bitmaps at the cascade width, or NULL
   uint32_t n;              // sets in the space
+  const uint64_t *bmw;     // wide bitmaps (kWideWords words per slot), or NULL
+  const uint32_t *wide_lo; // per side: first position with a wide bitmap (~0u: none)
+  const uint32_t *wide_slot; // per side: the slot of that position
 };
 
 // Verification of the queued survivors (sorted merge, Table 1 predicate)

@@ -100,3 +100,27 @@ def test_every_row_past_the_cutoff():
     got, st = ssj.ssj_self_join(_dev(c), 1, 2, b_bits=64, flags=CUT)
     assert np.array_equal(got, want)
     assert st["filter_ops"] == 0 and st["band_pairs"] == oracle.band_pairs(c.sizes(), 1, 2)
+
+
+@pytest.mark.parametrize("pq", [(1, 2), (7, 10), (4, 5)])
+def test_wide_bitmaps_for_large_sets(pq):
+    """Sets of 200-1500 tokens: pairs of sets above 256 tokens take a second
+    test at 4096 bits in verification (automatic widths), with and without
+    the cutoff.  The pairs must not change."""
+    p, q = pq
+    c = gen.generate(n_sets=1500, universe=4000, zipf_s=1.0, size_dist=gen.SIZE_UNIFORM,
+                     size_lo=200, size_hi=1500, planted_frac=0.4, seed=1600 + p)
+    r = gen.generate(n_sets=400, universe=4000, zipf_s=1.0, size_dist=gen.SIZE_UNIFORM,
+                     size_lo=200, size_hi=1500, planted_frac=0.4, seed=1700 + p)
+    want = oracle.self_join(c.offsets, c.tokens, p, q)
+    assert len(want) > 50
+    for fl in (0, CUT):
+        got, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=0, flags=fl)
+        assert np.array_equal(got, want), (p, q, fl)
+    want = oracle.rs_join(r.offsets, r.tokens, c.offsets, c.tokens, p, q)
+    for fl in (0, CUT):
+        got, _ = ssj.ssj_rs_join(_dev(r), _dev(c), p, q, b_bits=0, flags=fl)
+        assert np.array_equal(got, want), (p, q, fl)
+    with ssj.Index(_dev(c)) as idx:
+        got, _ = idx.query([_dev(r)], [p], [q])
+        assert np.array_equal(got[0], want)
