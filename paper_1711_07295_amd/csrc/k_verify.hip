@@ -4,8 +4,7 @@
 // Each queue entry (i, j) names a row and a column (global size-order
 // indices of the row and column spaces); the sets are the caller's CSR sets
 // perm[i] of side side_of[i] and perm[j] of side side_of[j], and the task is
-// the one of the row's side (of the column's side when the roles of an R-S
-// join are swapped).  The overlap o = |r n s| comes from one sorted merge
+// the one of the row's side.  The overlap o = |r n s| comes from one sorted merge
 // that stops as soon as even matching every remaining token could not reach
 // omin(|r|, |s|), the least overlap that meets the task's threshold
 // (Table 1, integer form).  A qualifying pair is written as a 64-bit key
@@ -79,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
     const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
     const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
     const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only, uint32_t w2,
-    uint32_t by_col, unsigned long long *__restrict__ results, unsigned long long results_cap,
+    unsigned long long *__restrict__ results, unsigned long long results_cap,
     JoinCounters *__restrict__ ctr) {
   const uint32_t lane = threadIdx.x & 63;
   unsigned long long count = ctr->queue_count;
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
         const uint32_t sr = rows.side_of[qe.x], sc = cols.side_of[qe.y];
         const SideDesc dr = rows.sides[sr];
         const SideDesc dc = cols.sides[sc];
-        const uint32_t task = by_col ? side_task[sc] : side_task[sr];
+        const uint32_t task = side_task[sr];
         const uint32_t x = rows.perm[qe.x], y = cols.perm[qe.y];
         const uint64_t r0 = dr.offsets[x], r1 = dr.offsets[x + 1];
         const uint64_t s0 = dc.offsets[y], s1 = dc.offsets[y + 1];
@@ -145,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
         }
         if (hit) {
           uint32_t ki = x, kj = y;
-          if (by_col || (tasks[task].self && y < x)) {
+          if (tasks[task].self && y < x) {
             ki = y;
             kj = x;
           }
@@ -199,14 +198,14 @@ __global__ __launch_bounds__(kBlock) void k_split_results(
 hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
                          VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
                          const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         uint32_t w2, uint32_t by_col, unsigned long long *results,
+                         uint32_t w2, unsigned long long *results,
                          unsigned long long results_cap, JoinCounters *ctr, hipStream_t st) {
   if ((rows.bm2 == nullptr) != (cols.bm2 == nullptr) || (rows.bm2 && !w2))
     return hipErrorInvalidValue;
   if ((rows.bmw == nullptr) != (cols.bmw == nullptr)) return hipErrorInvalidValue;
   dim3 grid(filter_grid_blocks());
   hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
-                     tasks, tables, ib, jb, survivors_only, w2, by_col, results, results_cap,
+                     tasks, tables, ib, jb, survivors_only, w2, results, results_cap,
                      ctr);
   return hipGetLastError();
 }

@@ -38,9 +38,6 @@ constexpr uint32_t kDefaultTileCols = 2048;
 constexpr uint64_t kMinSlotTiles = 16384;
 constexpr uint32_t kMinTileCols = 64;
 constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
-// An R-S join whose R side holds fewer than 1/kSwapRatio of S's sets runs
-// with the roles swapped (S as the rows).
-constexpr uint64_t kSwapRatio = 8;
 
 struct Fail {
   int code;
@@ -816,10 +813,7 @@ struct JoinConfig {
   uint64_t cap = kDefaultQueue;
   bool survivors_only = false;
   bool cutoff = false;         // rows past the cutoff point take prefix-filtered candidates
-  bool rows_resident = false;  // the row space is an index's: no bitmaps are added to it
   bool cols_resident = false;  // the column space is an index's
-  bool by_col = false;         // tasks are keyed by their column side, and the result pairs
-                               // are (column, row): the roles of a swapped R-S join
   bool mfma = true;            // matrix-core filter at the widths it exists for
 };
 
@@ -836,12 +830,12 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   pl.tasks.resize(n_tasks);
   std::vector<std::vector<WidthClass>> classes(n_tasks);
   std::vector<uint64_t> task_band(n_tasks, 0);
-  std::vector<uint32_t> side_task(jc.by_col ? C.n_sides : R.n_sides, 0xFFFFFFFFu);
+  std::vector<uint32_t> side_task(R.n_sides, 0xFFFFFFFFu);
   const uint32_t wpad = automatic ? 0 : filter_padded_words(jc.b_bits / 64);
   if (!automatic && !wpad) throw Fail{SSJ_E_UNSUPPORTED};
   for (uint32_t k = 0; k < n_tasks; ++k) {
     const TaskIn &tk = tasks[k];
-    const uint32_t key_side = jc.by_col ? tk.col_side : tk.row_side;
+    const uint32_t key_side = tk.row_side;
     if (side_task[key_side] != 0xFFFFFFFFu) throw Fail{SSJ_E_INVALID};
     side_task[key_side] = k;
     TaskDesc &td = pl.tasks[k];
@@ -911,21 +905,16 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   }
   // a resident space (an index's) already holds every width it may need
   for (uint32_t k = 0; k < nbw; ++k) {
-    if (jc.rows_resident && !R.bitmaps(bw[k])) throw Fail{SSJ_E_UNSUPPORTED};
     if (jc.cols_resident && !C.bitmaps(bw[k])) throw Fail{SSJ_E_UNSUPPORTED};
   }
-  if (!jc.rows_resident) space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st);
+  space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st);
   if (!jc.cols_resident) space_bitmaps_multi(C, bw, bb, nbw, ar, ctr, st);
   // sign planes for the widths the matrix-core kernel runs (an index holds
   // its own)
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     const uint32_t w = pl.slot_words[k];
     if (!filter_shape(w, jc.mfma).mfma) continue;
-    if (jc.rows_resident) {
-      if (!R.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
-    } else {
-      space_signs(R, w, ar, st);
-    }
+    space_signs(R, w, ar, st);
     if (jc.cols_resident) {
       if (!C.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
     } else {
@@ -934,8 +923,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   }
   if (pl.n_slots == 0) {
     // no bitmaps (every row past the cutoff): check the token order directly
-    if (!jc.rows_resident)
-      for (const auto &d : R.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
+    for (const auto &d : R.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
     if (&C != &R && !jc.cols_resident)
       for (const auto &d : C.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
   }
@@ -1067,12 +1055,10 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
   uint64_t res_cap = std::max<uint64_t>(qcap, 1024);
   unsigned long long *results = ar.alloc<unsigned long long>(res_cap);
-  // result keys (task, i, j): i of the row side, j of the column side, or
-  // the other way round for a swapped join
+  // result keys (task, i, j): i of the row side, j of the column side
   int ib = 1, jb = 1;
   for (const auto &d : R.h_sides) ib = std::max(ib, bits_for(d.n ? d.n - 1 : 0));
   for (const auto &d : C.h_sides) jb = std::max(jb, bits_for(d.n ? d.n - 1 : 0));
-  if (jc.by_col) std::swap(ib, jb);
   const int tb = bits_for(n_tasks > 1 ? n_tasks - 1 : 0);
   if (tb + ib + jb > 64) throw Fail{SSJ_E_UNSUPPORTED};
   // cascade width: the widest bitmaps both spaces hold, when wider than the
@@ -1084,7 +1070,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   // wide bitmaps for pairs of large sets (automatic mode, as the cascade);
   // an index holds its own
   if (cascade) {
-    if (!jc.rows_resident) space_wide(R, ar, st);
+    space_wide(R, ar, st);
     if (!jc.cols_resident) space_wide(C, ar, st);
   }
   const bool wide = cascade && R.bmw && C.bmw;
@@ -1135,7 +1121,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     t_verify.emplace_back();
     check(hipEventRecord(t_verify.back().ev[0], st));
     check(launch_verify(queue, qcap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
-                        jc.survivors_only ? 1u : 0u, w2, jc.by_col ? 1u : 0u, results, res_cap, ctr,
+                        jc.survivors_only ? 1u : 0u, w2, results, res_cap, ctr,
                         st));
     check(hipEventRecord(t_verify.back().ev[1], st));
     d2h(&ctr_h, ctr, 1, st);
@@ -1234,7 +1220,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
           res_cap = ncap;
         }
         check(launch_verify(pqueue, ccap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
-                            jc.survivors_only ? 1u : 0u, w2, jc.by_col ? 1u : 0u, results, res_cap, ctr,
+                            jc.survivors_only ? 1u : 0u, w2, results, res_cap, ctr,
                         st));
         d2h(&ctr_h, ctr, 1, st);
         sync(st);
@@ -1373,14 +1359,7 @@ int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const u
       if (!self) space_caller_bitmaps(B, s_bm, w, b_bits, ar, ctr, st);
     }
     std::vector<TaskIn> tasks{{0, 0, sim, p, q, self}};
-    if (!self && A.n * kSwapRatio < B.n) {
-      // a small R against a large S: swapped roles (see join_tasks)
-      JoinConfig js = jc;
-      js.by_col = true;
-      run_join(B, A, tasks, js, ar, ctr, st, t_prep, jo, stats);
-    } else {
-      run_join(A, C, tasks, jc, ar, ctr, st, t_prep, jo, stats);
-    }
+    run_join(A, C, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
     std::free(jo.pairs);
     (void)hipGetLastError();
@@ -1435,26 +1414,12 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
       sides[k] = rows + k;
     }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    // A query side much smaller than the resident collection joins with
-    // the roles swapped: the resident sets are the rows (their bitmaps read
-    // once per tile) and the query sets the columns (small enough to stay
-    // in the caches the filter's column loads go through).
-    bool swap = false;
     if (idx) {
       int dev = 0;
       check(hipGetDevice(&dev));
       if (dev != idx->device) return SSJ_E_INVALID;
       jc.b_bits = idx->b_bits;
-      uint64_t nq = 0;
-      for (uint32_t k = 0; k < n; ++k) nq += rows[k].n_sets;
-      swap = nq * kSwapRatio < idx->S.n;
-      if (swap) {
-        jc.rows_resident = true;
-        jc.by_col = true;
-        for (uint32_t k = 0; k < n; ++k) std::swap(tasks[k].row_side, tasks[k].col_side);
-      } else {
-        jc.cols_resident = true;
-      }
+      jc.cols_resident = true;
     }
     Arena ar(st);
     Timer t_prep;
@@ -1467,8 +1432,7 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
     space_sort(A, true, ar, ar, st);
     sync(st);
     space_finish(A);
-    if (swap) run_join(idx->S, A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
-    else run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
+    run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
     std::free(jo.pairs);
     (void)hipGetLastError();

@@ -311,12 +311,12 @@ struct VerifySpace {
 // indices (self-join pairs as (min, max)).  side_task[s]: the task of row
 // side s.
 // w2: words of the cascade bitmaps (rows.bm2 and cols.bm2 both set, or
-// both NULL for no second test).  by_col: side_task is indexed by the
-// column side and keys are (task, column caller index, row caller index).
+// both NULL for no second test); rows.bmw and cols.bmw likewise for the
+// wide test.
 hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
                          VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
                          const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         uint32_t w2, uint32_t by_col, unsigned long long *results,
+                         uint32_t w2, unsigned long long *results,
                          unsigned long long results_cap, JoinCounters *ctr, hipStream_t st);
 
 // Sorted result keys -> ssj_pair {i, j}; task_start[k] = first result of

@@ -148,9 +148,9 @@ def test_index_outlives_the_callers_collection_and_edge_cases():
 
 
 @pytest.mark.parametrize("b", [0, 64, 128])
-def test_rs_join_with_small_r_swaps_roles(b):
-    """|R| * 8 < |S| runs with S as the rows and R as the columns; the pairs
-    are still (i in R, j in S), ascending."""
+def test_rs_join_with_small_r(b):
+    """A small R against a large S (few row blocks, long column bands); the
+    pairs are (i in R, j in S), ascending."""
     s = _col(900, 4000, universe=600, hi=120, median=20.0, planted=0.3)
     r = gen.from_lists([s.set(k) for k in range(0, 4000, 60)] +
                        [_col(901, 50, universe=600, hi=120, median=20.0).set(k) for k in range(50)])
@@ -166,7 +166,7 @@ def test_rs_join_with_small_r_swaps_roles(b):
             assert st["band_pairs"] == oracle.band_pairs_rs(r.sizes(), s.sizes(), p, q, sim=osim)
 
 
-def test_index_small_batches_swap_roles():
+def test_index_small_batches():
     sw = gen.served_workload(6, resident_sets=8000, max_batch=60, seed=gen.SEED_BASE + 41)
     res = sw.resident
     with ssj.Index(_dev(res)) as idx:
