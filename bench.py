@@ -35,14 +35,15 @@ PEAK_HBM = 8.0e12                 # bytes/s
 MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
 
 # HBM bytes per launch of the dominant filter launch (the b = 64 class of the
-# 1,000,000-set workload at 4/5), from two rocprofv3 --pmc passes (FETCH_SIZE,
-# WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for a
-# 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it: factor 2.0; WRITE_SIZE
-# 1 GiB: factor 1.0).  Valid only for the kernel sources they were taken
-# with: any change to them makes the figure null until the counters are taken
-# again.  The summary and commands are in profiles/.
-TRAFFIC = {"sources_sha256": "7e65f097d9df9bb93cbbd38b1c453ebcae038db29ce28009abc6d7a733ceaa30",
-           "fetch_kib": 34056.1, "write_kib": 19588.8,
+# 1,000,000-set workload at 4/5, matrix-core kernel), from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the
+# same counters read for a 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for
+# it: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0).  Valid only for the kernel
+# sources they were taken with: any change to them makes the figure null
+# until the counters are taken again.  The summary and commands are in
+# profiles/.
+TRAFFIC = {"sources_sha256": "68a54c0ff32d4eb9fe19dc72c149af8df0a45fd56591b3fc53ebd63d404328ca",
+           "fetch_kib": 86323.5, "write_kib": 43434.2,
            "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
