@@ -43,7 +43,7 @@ MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
 # until the counters are taken again.  The summary and commands are in
 # profiles/.
 TRAFFIC = {"sources_sha256": "68a54c0ff32d4eb9fe19dc72c149af8df0a45fd56591b3fc53ebd63d404328ca",
-           "fetch_kib": 86323.5, "write_kib": 43434.2,
+           "fetch_kib": 85852.2, "write_kib": 20499.2,
            "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
@@ -94,8 +94,8 @@ def main():
                     help="serve mode: measured batches per load (plus 100 warm-up)")
     ap.add_argument("--resident", type=int, default=5_000_000,
                     help="serve mode: sets in the resident index")
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin-1m")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--q", type=int, default=5)

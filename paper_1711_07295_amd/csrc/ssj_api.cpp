@@ -1044,11 +1044,16 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   // and writes staged runs (at most kFilterStage pairs) into its chunk; the
   // queue must hold at least one chunk, or a run could never be written and
   // its tile never resumed.  Chunks are small against the queue, so that
-  // many waves hold one in a round (at most 1024 slots each: the unused end
-  // of a chunk costs verification a sentinel read per slot).
+  // many waves hold one in a round.  The unused end of a chunk costs
+  // verification a sentinel read per slot, a reservation costs an atomic on
+  // one address.  The width classes below the widest automatic width keep
+  // false survivors rare (their widths are chosen for it), so their waves
+  // take kFilterStage slots at a time; the widest class (every size beyond
+  // the others, where the bits saturate) and a fixed width can keep many
+  // pairs, and their waves take up to 1024.
   static_assert(kFilterStage <= 4096, "the queue holds at least 4096 entries");
   const uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
-  const uint32_t chunk =
+  const uint32_t dense_chunk =
       (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
   uint2 *queue = ar.alloc<uint2>(qcap);
   const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
@@ -1095,7 +1100,6 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   cfg.n_blocks = (uint32_t)nB;
   cfg.resume_cap = max_waves;
   cfg.cap = qcap;
-  cfg.chunk = chunk;
   for (;;) {
     if (pl.n_tiles == 0) break;
     cfg.n_resume_in = n_resume_in;
@@ -1107,6 +1111,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       cfg.tile_hi = pl.tile_hi[k];
       cfg.tile_cols = pl.slot_tile_cols[k];
       cfg.cls = k;
+      cfg.chunk = automatic && pl.slot_words[k] < kAutoWords[3] ? kFilterStage : dense_chunk;
       const uint32_t w = pl.slot_words[k];
       const bool mf = filter_shape(w, jc.mfma).mfma;
       FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
