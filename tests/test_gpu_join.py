@@ -217,6 +217,27 @@ def test_automatic_width_classes_match_oracle(pq):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("flags", [0, ssj.SSJ_FLAG_SURVIVORS_ONLY])
+def test_width_classes_drain_together(flags):
+    """Automatic widths with the smallest queue: the queue fills in the
+    launches of several width classes, each resuming from its own tiles in
+    later rounds.  Pairs and survivor sets equal those of one pass with a
+    large queue, and the pairs equal the oracle's."""
+    c = gen.generate(n_sets=5000, universe=600, zipf_s=1.0, size_dist=gen.SIZE_LOGNORMAL,
+                     size_a=40.0, size_b=1.0, size_lo=1, size_hi=400, planted_frac=0.3,
+                     seed=404)
+    d = _dev(c)
+    one, s1 = ssj.ssj_self_join(d, 1, 3, b_bits=0, flags=flags)
+    got, st = ssj.ssj_self_join(d, 1, 3, b_bits=0, flags=flags, queue_capacity=1)
+    assert st["n_classes"] >= 3
+    assert s1["filter_launches"] == s1["n_classes"]
+    assert s1["survivors"] > 3 * 4096 and st["filter_launches"] >= 3 * st["n_classes"]
+    assert st["survivors"] == s1["survivors"] and st["results"] == s1["results"]
+    assert np.array_equal(got, one)
+    if not flags:
+        assert np.array_equal(got, oracle.self_join(c.offsets, c.tokens, 1, 3))
+
+
 def test_automatic_width_rejects_caller_bitmaps():
     c = _ragged(61, n=100)
     d = _dev(c)
