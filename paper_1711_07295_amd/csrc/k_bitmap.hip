@@ -228,14 +228,14 @@ hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint3
   return hipGetLastError();
 }
 
-// Sign planes: one thread per (set, 64-bit block, half), for n + 1 sets: set
-// n is all zero.  Each half of 32 bits becomes four dwords of fp4 nibbles,
+// Sign planes: one thread per (set, 64-bit block, half), for n + kSignPad
+// sets: the sets from n on are all zero.  Each half of 32 bits becomes four dwords of fp4 nibbles,
 // +1 (0x2) for a set bit and -1 (0xA) for a clear one.
 __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restrict__ bm,
                                                           uint32_t words, uint64_t n,
                                                           uint4 *__restrict__ planes) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (n + 1) * words * 2) return;
+  if (t >= (n + kSignPad) * words * 2) return;
   const uint32_t h = (uint32_t)(t & 1);
   const uint64_t sw = t >> 1;
   const uint64_t s = sw / words;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restr
     }
     out = make_uint4(d[0], d[1], d[2], d[3]);
   }
-  planes[((uint64_t)kb * (n + 1) + s) * 2 + h] = out;
+  planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
 }
 
 // Wide Bitmap-Xor bitmaps of the sets in the wide ranges: one wave per set,
@@ -351,7 +351,7 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
 hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
                                hipStream_t st) {
   if (words == 0) return hipErrorInvalidValue;
-  const uint64_t total = (n + 1) * words * 2;
+  const uint64_t total = (n + kSignPad) * words * 2;
   hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, st, bm, words, n, planes);
   return hipGetLastError();

@@ -541,6 +541,12 @@ template <int W, int RT>
 struct MRows {
   uint4 sg[RT][W];  // this lane's half of every 64-bit block of its row in each row tile
   float thr[RT];    // dot threshold for the current size group
+  // the same threshold for the fast test, which compares the bit patterns
+  // of the dot products as integers: for a positive threshold those order
+  // like the values (every value is an exact integer, +0 included, and the
+  // negative ones fall below every positive pattern); a threshold of 0 or
+  // less becomes INT32_MIN, so that every step goes to the exact test
+  int32_t thr_bits[RT];
   uint32_t size[RT];
   uint32_t cmn[RT];
   uint32_t cmx[RT];
@@ -557,12 +563,28 @@ __device__ __forceinline__ v16f_t mfma_pm1(const uint4 &a, const uint4 &b, const
 // This lane's half of every block of column `col`, or zeros when !ok: the
 // planes hold n + 1 columns, column n all zero, so every lane loads and no
 // load sits behind a branch.
+// This lane's half of set `col`'s sign planes (set n, all zero, when !ok).
 template <int W>
 __device__ __forceinline__ void load_signs(const uint4 *__restrict__ planes, uint32_t n,
                                            uint32_t col, bool ok, uint32_t h, uint4 (&a)[W]) {
   const size_t c = ok ? col : n;
 #pragma unroll
-  for (int kb = 0; kb < W; ++kb) a[kb] = planes[((size_t)kb * (n + 1) + c) * 2 + h];
+  for (int kb = 0; kb < W; ++kb) a[kb] = planes[((size_t)kb * (n + kSignPad) + c) * 2 + h];
+}
+
+// The columns j0 + (lane % 32) of one step: a uniform address (j0 is the
+// same in every lane) plus the lane's byte offset loff = 32 (lane % 32) +
+// 16 h.  No bounds test: the zero padding past set n - 1 covers loads up to
+// 95 columns past a column below n, and the pairs of columns past the size
+// group's end are dropped by the exact test.
+template <int W>
+__device__ __forceinline__ void load_cols(const uint4 *__restrict__ planes, uint32_t n,
+                                          uint32_t j0, uint32_t loff, uint4 (&a)[W]) {
+#pragma unroll
+  for (int kb = 0; kb < W; ++kb) {
+    const uint4 *p = planes + ((size_t)kb * (n + kSignPad) + j0) * 2;
+    a[kb] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(p) + loff);
+  }
 }
 
 // Stage one ballot mask of kept pairs (row `row` of the lanes' row tile is
@@ -607,7 +629,7 @@ __device__ __forceinline__ bool stage_mask(unsigned long long m, uint32_t row, u
 // `skip` pairs it had written.
 template <int W, int RT>
 __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&a)[W],
-                                          const float (&mx)[RT], uint32_t j0, uint32_t gend,
+                                          const int32_t (&mx)[RT], uint32_t j0, uint32_t gend,
                                           bool diag, uint32_t &skip, Sink &sink) {
   constexpr uint32_t kFewLanes = 4;
   const uint32_t lane = threadIdx.x & 63, h = lane >> 5;
@@ -616,7 +638,7 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
   uint32_t done = 0;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    if (!__ballot(mx[rt] >= rw.thr[rt])) continue;
+    if (!__ballot(mx[rt] >= rw.thr_bits[rt])) continue;
     // the step's dot products of this row tile again (the fast path does
     // not keep them: registers are what limits the waves per SIMD)
     v16f_t d = {};
@@ -669,31 +691,36 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
 }
 
 // Fast path of one step: columns [j0, j0 + 32) against the wave's rows.
-// Leaves each row tile's best value in mx and returns whether some value
-// reaches its threshold.
+// Leaves each row tile's largest bit pattern (as an integer) in mx and
+// returns whether one reaches its threshold (thr_bits).  Integer maxima:
+// float maxima would first quiet possible signalling NaNs, two more
+// instructions per row tile.
 template <int W, int RT>
 __device__ __forceinline__ bool fast_mfma(const uint4 (&a)[W], const MRows<W, RT> &rw,
-                                          float (&mx)[RT]) {
+                                          int32_t (&mx)[RT]) {
   // Two accumulators: row tile rt's products go into the registers of row
   // tile rt-2 once those are reduced, so one row tile's MFMA runs while the
   // previous one is reduced and fewer registers hold dot products (the
   // waves per SIMD are bounded by registers).
-  float best = -kNever;
+  unsigned long long hit = 0;
   v16f_t acc[2];
 #pragma unroll
   for (int rt = 0; rt < RT + 2; ++rt) {
     if (rt >= 2) {
       const v16f_t &x = acc[rt & 1];
-      // max of the 16 values, as a tree of 3-input maxima
-      float m0 = __builtin_fmaxf(__builtin_fmaxf(x[0], x[1]), x[2]);
-      float m1 = __builtin_fmaxf(__builtin_fmaxf(x[3], x[4]), x[5]);
-      float m2 = __builtin_fmaxf(__builtin_fmaxf(x[6], x[7]), x[8]);
-      float m3 = __builtin_fmaxf(__builtin_fmaxf(x[9], x[10]), x[11]);
-      float m4 = __builtin_fmaxf(__builtin_fmaxf(x[12], x[13]), x[14]);
-      m0 = __builtin_fmaxf(__builtin_fmaxf(m0, m1), m2);
-      m3 = __builtin_fmaxf(__builtin_fmaxf(m3, m4), x[15]);
-      mx[rt - 2] = __builtin_fmaxf(m0, m3);
-      best = __builtin_fmaxf(best, mx[rt - 2] - rw.thr[rt - 2]);
+      int32_t b[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) b[v] = __float_as_int(x[v]);
+      // max of the 16 patterns, as a tree of 3-input maxima
+      int32_t m0 = max(max(b[0], b[1]), b[2]);
+      int32_t m1 = max(max(b[3], b[4]), b[5]);
+      int32_t m2 = max(max(b[6], b[7]), b[8]);
+      int32_t m3 = max(max(b[9], b[10]), b[11]);
+      int32_t m4 = max(max(b[12], b[13]), b[14]);
+      m0 = max(max(m0, m1), m2);
+      m3 = max(max(m3, m4), b[15]);
+      mx[rt - 2] = max(m0, m3);
+      hit |= __ballot(mx[rt - 2] >= rw.thr_bits[rt - 2]);
     }
     if (rt < RT) {
       v16f_t t = {};
@@ -703,64 +730,71 @@ __device__ __forceinline__ bool fast_mfma(const uint4 (&a)[W], const MRows<W, RT
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  return __ballot(best >= 0.f) != 0;
+  return hit != 0;
 }
 
 // The steps of columns [j, g1) of one size group.  Column loads run two
 // steps ahead in a ring of three register buffers; the loop is unrolled by
 // three so that the ring turns without register copies (a copy of a buffer
-// still being loaded would wait for that load).  The three steps share one
-// slow path, laid out once: a step that keeps something copies its own
-// buffer (loaded by then) and jumps there, and the slow path returns to
-// the step after it.  Instruction cache: the kernel stays small.
+// still being loaded would wait for that load).  A step that keeps
+// something leaves the loop for the one slow path, laid out once
+// (instruction cache: the kernel stays small); the slow path turns the
+// ring by register moves so that the loop goes on at the next step with
+// the buffers already loaded.  Every branch leaves the loop, none enters
+// it in the middle, and every buffer is read on both sides of each exit:
+// the compiler keeps the ring in fixed registers and leaves the loads
+// where they are.
 template <int W, int RT>
 __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, uint32_t n_cols,
                                            const MRows<W, RT> &rw, uint32_t j, uint32_t g1,
                                            bool diag, uint32_t &skip, Sink &sink) {
-  const uint32_t lane = threadIdx.x & 63, h = lane >> 5, jr = lane & 31;
-  uint4 b0[W], b1[W], b2[W], cur[W];
-  float mx[RT];
-  int phase = 0;
-  load_signs<W>(sg_cols, n_cols, j + jr, j + jr < g1, h, b0);
-  load_signs<W>(sg_cols, n_cols, j + 32 + jr, j + 32 + jr < g1, h, b1);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t loff = (lane & 31u) * 32u + (lane >> 5) * 16u;
+  uint4 b0[W], b1[W], b2[W];
+  int32_t mx[RT];
   uint32_t j0 = j;
-step0:
-  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b2);
-  if (__builtin_expect(fast_mfma<W, RT>(b0, rw, mx), 0)) {
+  load_cols<W>(sg_cols, n_cols, j0, loff, b0);
+  load_cols<W>(sg_cols, n_cols, j0 + 32, loff, b1);
+  for (;;) {
+    int phase;  // the ring buffer that holds the columns of step j0
+    for (;;) {
+      load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b2);
+      if (__builtin_expect(fast_mfma<W, RT>(b0, rw, mx), 0)) {
+        phase = 0;
+        break;
+      }
+      skip = 0;
+      if ((j0 += 32) >= g1) return true;
+      load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b0);
+      if (__builtin_expect(fast_mfma<W, RT>(b1, rw, mx), 0)) {
+        phase = 1;
+        break;
+      }
+      skip = 0;
+      if ((j0 += 32) >= g1) return true;
+      load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b1);
+      if (__builtin_expect(fast_mfma<W, RT>(b2, rw, mx), 0)) {
+        phase = 2;
+        break;
+      }
+      skip = 0;
+      if ((j0 += 32) >= g1) return true;
+    }
+    uint4 cur[W];
 #pragma unroll
-    for (int kb = 0; kb < W; ++kb) cur[kb] = b0[kb];
-    phase = 0;
-    goto slow;
-  }
-after0:
-  skip = 0;
-  if ((j0 += 32) >= g1) return true;
-  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b0);
-  if (__builtin_expect(fast_mfma<W, RT>(b1, rw, mx), 0)) {
+    for (int kb = 0; kb < W; ++kb) cur[kb] = phase == 0 ? b0[kb] : phase == 1 ? b1[kb] : b2[kb];
+    if (!emit_mfma<W, RT>(rw, cur, mx, j0, g1, diag, skip, sink)) return false;
+    skip = 0;
+    if ((j0 += 32) >= g1) return true;
+    // b0 and b1 take the columns of steps j0 and j0 + 32
 #pragma unroll
-    for (int kb = 0; kb < W; ++kb) cur[kb] = b1[kb];
-    phase = 1;
-    goto slow;
+    for (int kb = 0; kb < W; ++kb) {
+      const uint4 x0 = phase == 0 ? b1[kb] : phase == 1 ? b2[kb] : b0[kb];
+      const uint4 x1 = phase == 0 ? b2[kb] : phase == 1 ? b0[kb] : b1[kb];
+      b0[kb] = x0;
+      b1[kb] = x1;
+    }
   }
-after1:
-  skip = 0;
-  if ((j0 += 32) >= g1) return true;
-  load_signs<W>(sg_cols, n_cols, j0 + 64 + jr, j0 + 64 + jr < g1, h, b1);
-  if (__builtin_expect(fast_mfma<W, RT>(b2, rw, mx), 0)) {
-#pragma unroll
-    for (int kb = 0; kb < W; ++kb) cur[kb] = b2[kb];
-    phase = 2;
-    goto slow;
-  }
-after2:
-  skip = 0;
-  if ((j0 += 32) >= g1) return true;
-  goto step0;
-slow:
-  if (!emit_mfma<W, RT>(rw, cur, mx, j0, g1, diag, skip, sink)) return false;
-  if (phase == 0) goto after0;
-  if (phase == 1) goto after1;
-  goto after2;
 }
 
 // One tile on the matrix cores: rows [row0, row_end) (at most 32*RT),
@@ -803,7 +837,11 @@ __device__ __forceinline__ bool run_tile_mfma(const uint4 *__restrict__ sg_rows,
       int32_t sl = 0;
       if (in_band) sl = (COS && jb.cosine) ? cosine_slack(rw.size[rt], c, jb.p, jb.q)
                                            : jb.slack[rw.size[rt] + c];
-      rw.thr[rt] = in_band ? (float)(K - 2 * sl) : kNever;
+      const int32_t t = K - 2 * sl;
+      rw.thr[rt] = in_band ? (float)t : kNever;
+      rw.thr_bits[rt] = !in_band ? __float_as_int(kNever)
+                        : t > 0  ? __float_as_int((float)t)
+                                 : INT32_MIN;
       any_ok |= in_band;
     }
     if (__ballot(any_ok)) {

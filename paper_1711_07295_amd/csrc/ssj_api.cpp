@@ -330,7 +330,7 @@ void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st) {
   for (uint32_t k = 0; k < sp.n_bm; ++k) {
     if (sp.bm_words[k] != words) continue;
     if (sp.sg[k]) return;
-    uint4 *planes = ar.alloc<uint4>((sp.n + 1) * words * 2);
+    uint4 *planes = ar.alloc<uint4>((sp.n + kSignPad) * words * 2);
     check(launch_expand_signs(sp.bm[k], words, sp.n, planes, st));
     sp.sg[k] = planes;
     return;

@@ -223,10 +223,13 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
 // Sign planes of bitmaps for the matrix-core filter: bit k of a set's
 // bitmap becomes the fp4 (e2m1) value +1 (0x2) when set and -1 (0xA) when
 // clear.  64-bit block kb of set s is stored as two uint4 halves at
-// planes[(kb * (n + 1) + s) * 2 + h]; half h holds bits 32h..32h+31 of the
-// block, bit 8e+m of a half in nibble m of its dword e.  Set n is all zero
-// (lanes with no set load it).  `bm`: n sets of `words` words, in the
-// order the planes take; planes: (n + 1) * words * 2 entries.
+// planes[(kb * (n + kSignPad) + s) * 2 + h]; half h holds bits 32h..32h+31
+// of the block, bit 8e+m of a half in nibble m of its dword e.  Sets n ..
+// n + kSignPad - 1 are all zero: lanes with no row load set n, and a step's
+// column loads (at most 95 columns past a column below n) stay inside the
+// plane without a bounds test.  `bm`: n sets of `words` words, in the
+// order the planes take; planes: (n + kSignPad) * words * 2 entries.
+constexpr uint32_t kSignPad = 96;
 hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
                                hipStream_t st);
 
