@@ -42,8 +42,8 @@ MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
 # sources they were taken with: any change to them makes the figure null
 # until the counters are taken again.  The summary and commands are in
 # profiles/.
-TRAFFIC = {"sources_sha256": "68a54c0ff32d4eb9fe19dc72c149af8df0a45fd56591b3fc53ebd63d404328ca",
-           "fetch_kib": 85852.2, "write_kib": 20499.2,
+TRAFFIC = {"sources_sha256": "6bd1fdd94e49e52ded8225f3581056f69672d1cd91d2b894f656a8cbb942f558",
+           "fetch_kib": 79519.1, "write_kib": 20661.1,
            "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
