@@ -195,6 +195,22 @@ __global__ __launch_bounds__(kBlock) void k_split_results(
 
 }  // namespace
 
+// Blocks of k_verify resident at once on the current device.  The grid
+// strides over the queue with a fixed share per lane: blocks beyond what
+// the compute units hold would start only when the first ones end, and the
+// launch would take two rounds of its latency-bound loop instead of one.
+static int verify_grid_blocks() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_verify, kBlock, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  return cus * per_cu;
+}
+
 hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
                          VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
                          const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
@@ -203,7 +219,7 @@ hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace
   if ((rows.bm2 == nullptr) != (cols.bm2 == nullptr) || (rows.bm2 && !w2))
     return hipErrorInvalidValue;
   if ((rows.bmw == nullptr) != (cols.bmw == nullptr)) return hipErrorInvalidValue;
-  dim3 grid(filter_grid_blocks());
+  dim3 grid(verify_grid_blocks());
   hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
                      tasks, tables, ib, jb, survivors_only, w2, results, results_cap,
                      ctr);
