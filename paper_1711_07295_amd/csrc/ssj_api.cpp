@@ -34,9 +34,14 @@ namespace {
 constexpr uint64_t kDefaultQueue = 1ull << 29;   // 4 GiB of (row, column) pairs
 constexpr uint32_t kDefaultTileCols = 2048;
 // A width class with fewer than about kMinSlotTiles tiles of the default
-// width gets narrower tiles, down to kMinTileCols columns.
+// width gets narrower tiles, down to kMinTileCols columns; kMinTileColsValu
+// for the vector-ALU kernel, whose classes hold the largest sets: on the
+// sparse tail of the size distribution a tile crosses a size group every
+// few columns, and the launch lasts as long as its slowest tile.  (The
+// matrix-core kernel measured no gain below 64: it takes 32 columns a step.)
 constexpr uint64_t kMinSlotTiles = 16384;
 constexpr uint32_t kMinTileCols = 64;
+constexpr uint32_t kMinTileColsValu = 32;
 constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
 
 struct Fail {
@@ -943,9 +948,10 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
           prev = c.max_size;
         }
       }
-      const uint64_t rows = filter_shape(pl.slot_words[k], pl.mfma).rows;
-      const uint64_t want = slot_band / (rows * kMinSlotTiles);
-      tile_cols = (uint32_t)std::max<uint64_t>(kMinTileCols, std::min<uint64_t>(tile_cols, want));
+      const FilterShape shape = filter_shape(pl.slot_words[k], pl.mfma);
+      const uint64_t want = slot_band / ((uint64_t)shape.rows * kMinSlotTiles);
+      const uint32_t floor_cols = shape.mfma ? kMinTileCols : kMinTileColsValu;
+      tile_cols = (uint32_t)std::max<uint64_t>(floor_cols, std::min<uint64_t>(tile_cols, want));
     }
     pl.slot_tile_cols[k] = tile_cols;
     pl.tile_lo[k] = pl.n_tiles;
