@@ -25,6 +25,7 @@ SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT = 0, 1, 2
 SSJ_FLAG_SURVIVORS_ONLY = 1
 SSJ_FLAG_CUTOFF = 2
 SSJ_FLAG_VALU = 4
+SSJ_FLAG_MFMA = 8
 
 EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
            "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_cutoff",

@@ -42,6 +42,11 @@ constexpr uint32_t kDefaultTileCols = 2048;
 constexpr uint64_t kMinSlotTiles = 16384;
 constexpr uint32_t kMinTileCols = 64;
 constexpr uint32_t kMinTileColsValu = 32;
+// A width class of fewer band pairs than this runs on the vector ALUs even
+// where a matrix-core shape exists: the matrix-core launch has the larger
+// fixed cost (about 0.12 ms against 0.07 ms for a class of 1.6e6 pairs at
+// b = 256), and below this the fixed cost dominates.
+constexpr uint64_t kMfmaMinBand = 1ull << 26;
 constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
 
 struct Fail {
@@ -650,8 +655,10 @@ struct Plan {
   uint64_t band_pairs = 0;
   uint64_t filter_ops = 0;       // sum over band pairs of b/16 + 1
   bool mfma = true;              // matrix-core filter where it exists (row block height)
-  // per width slot: its tiles [tile_lo[k], tile_hi[k]), padded width, work
+  // per width slot: its tiles [tile_lo[k], tile_hi[k]), padded width, work,
+  // and whether the matrix-core kernel runs it
   uint32_t n_slots = 0;
+  bool slot_mfma[kMaxClasses] = {false, false, false, false};
   uint32_t slot_words[kMaxClasses] = {0, 0, 0, 0};
   uint32_t slot_bits[kMaxClasses] = {0, 0, 0, 0};
   uint32_t slot_max_size[kMaxClasses] = {0, 0, 0, 0};
@@ -697,7 +704,7 @@ void add_tables(Plan &pl, TaskDesc &td, uint64_t a_max, uint64_t c_max, int sim,
 // added to band_out.
 void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint32_t task_id,
                 uint32_t lo, uint32_t hi, uint32_t words, uint32_t bits, uint32_t tile_cols,
-                uint64_t &band_out, bool count_only = false) {
+                bool mfma, uint64_t &band_out, bool count_only = false) {
   const TaskDesc &td = pl.tasks[task_id];
   const uint32_t *rs = R.ss(tk.row_side), *cs = C.ss(tk.col_side);
   const uint64_t a_max = R.side_max[tk.row_side], c_max = C.side_max[tk.col_side];
@@ -706,7 +713,7 @@ void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint
   const uint32_t col_base = (uint32_t)C.h_sides[tk.col_side].base;
   const uint32_t *cmin = pl.tables.data() + td.cmin_off;
   const uint32_t *cmax = pl.tables.data() + td.cmax_off;
-  const FilterShape shape = filter_shape(words, pl.mfma);
+  const FilterShape shape = filter_shape(words, mfma);
   auto col_lo = [&](uint64_t a) -> uint32_t {  // first column with size >= cmin[a]
     const uint64_t c = cmin[a];
     return c > c_max ? col_n : cs[c];
@@ -820,6 +827,7 @@ struct JoinConfig {
   bool cutoff = false;         // rows past the cutoff point take prefix-filtered candidates
   bool cols_resident = false;  // the column space is an index's
   bool mfma = true;            // matrix-core filter at the widths it exists for
+  bool mfma_always = false;    // ... for every width class, whatever its band pairs
 };
 
 // Plans and runs the tasks over prepared spaces R (rows) and C (columns; C
@@ -896,6 +904,24 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     pl.slot_bits[0] = jc.b_bits;
     pl.n_slots = 1;
   }
+  // band pairs of each slot, and its kernel: the matrix cores where the
+  // width has a matrix-core shape and the slot holds at least kMfmaMinBand
+  // band pairs (or the caller asked for them), else the vector ALUs, whose
+  // launch costs less
+  uint64_t slot_band[kMaxClasses] = {0, 0, 0, 0};
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    for (uint32_t t = 0; t < n_tasks; ++t) {
+      uint32_t prev = 0;
+      for (auto &c : classes[t]) {
+        if (c.words == pl.slot_words[k])
+          plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
+                     jc.tile_cols, false, slot_band[k], true);
+        prev = c.max_size;
+      }
+    }
+    pl.slot_mfma[k] = filter_shape(pl.slot_words[k], pl.mfma).mfma &&
+                      (jc.mfma_always || slot_band[k] >= kMfmaMinBand);
+  }
   // the widths to build: every class's, and in automatic mode the widest
   // automatic width for the cascade test of verification (same pass)
   uint32_t bw[kMaxClasses + 1], bb[kMaxClasses + 1], nbw = 0;
@@ -918,7 +944,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   // its own)
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     const uint32_t w = pl.slot_words[k];
-    if (!filter_shape(w, jc.mfma).mfma) continue;
+    if (!pl.slot_mfma[k]) continue;
     space_signs(R, w, ar, st);
     if (jc.cols_resident) {
       if (!C.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
@@ -938,18 +964,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     uint32_t tile_cols = jc.tile_cols;
     if (!jc.tile_cols_fixed) {
-      uint64_t slot_band = 0;
-      for (uint32_t t = 0; t < n_tasks; ++t) {
-        uint32_t prev = 0;
-        for (auto &c : classes[t]) {
-          if (c.words == pl.slot_words[k])
-            plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
-                       tile_cols, slot_band, true);
-          prev = c.max_size;
-        }
-      }
-      const FilterShape shape = filter_shape(pl.slot_words[k], pl.mfma);
-      const uint64_t want = slot_band / ((uint64_t)shape.rows * kMinSlotTiles);
+      const FilterShape shape = filter_shape(pl.slot_words[k], pl.slot_mfma[k]);
+      const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * kMinSlotTiles);
       const uint32_t floor_cols = shape.mfma ? kMinTileCols : kMinTileColsValu;
       tile_cols = (uint32_t)std::max<uint64_t>(floor_cols, std::min<uint64_t>(tile_cols, want));
     }
@@ -961,7 +977,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       for (auto &c : classes[t]) {
         if (c.words == pl.slot_words[k]) {
           plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
-                     tile_cols, task_band[t]);
+                     tile_cols, pl.slot_mfma[k], task_band[t]);
           pl.slot_max_size[k] = std::max(pl.slot_max_size[k], c.max_size);
         }
         prev = c.max_size;
@@ -980,7 +996,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     const TaskIn &tk = tasks[k];
     const uint32_t a_max = R.side_max[tk.row_side];
     uint64_t pb = 0;
-    plan_class(pl, R, C, tk, k, omega[k], a_max, 1, 64, jc.tile_cols, pb, true);
+    plan_class(pl, R, C, tk, k, omega[k], a_max, 1, 64, jc.tile_cols, false, pb, true);
     pl.band_pairs += pb;
     task_band[k] += pb;
     // probe prefix: |r| - omin(|r|, cmin(|r|)) + 1 tokens, the longest any
@@ -1119,7 +1135,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       cfg.cls = k;
       cfg.chunk = automatic && pl.slot_words[k] < kAutoWords[3] ? kFilterStage : dense_chunk;
       const uint32_t w = pl.slot_words[k];
-      const bool mf = filter_shape(w, jc.mfma).mfma;
+      const bool mf = pl.slot_mfma[k];
       FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
                     mf ? C.signs(w) : nullptr, R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
                     d_blocks, d_tile_block, queue, ctr, res_a, res_b, cfg};
@@ -1321,6 +1337,8 @@ JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
   jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
   jc.cutoff = opts && (opts->flags & SSJ_FLAG_CUTOFF);
   jc.mfma = !(opts && (opts->flags & SSJ_FLAG_VALU));
+  jc.mfma_always = opts && (opts->flags & SSJ_FLAG_MFMA);
+  if (!jc.mfma && jc.mfma_always) throw Fail{SSJ_E_INVALID};
   return jc;
 }
 

@@ -3,7 +3,10 @@ vector-ALU kernel (SSJ_FLAG_VALU).  The matrix cores score the Hamming
 distance of Theorem 1 as a dot product of +-1 vectors, exact in fp32, so
 both kernels must keep exactly the same pairs: the survivor sets
 (SSJ_FLAG_SURVIVORS_ONLY) are compared whole, also through queue drains
-that resume inside a step."""
+that resume inside a step.  These inputs are small, so SSJ_FLAG_MFMA puts
+every width class on the matrix cores (by default a class this small runs
+on the vector ALUs, whose launch costs less); one test also checks that
+default."""
 import numpy as np
 import pytest
 
@@ -15,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 SURV = ssj.SSJ_FLAG_SURVIVORS_ONLY
 VALU = ssj.SSJ_FLAG_VALU
+MF = ssj.SSJ_FLAG_MFMA
 
 
 def _dev(c):
@@ -33,7 +37,7 @@ def test_self_join_survivors_equal_oracle_and_valu(b, pq):
     p, q = pq
     c = _coll(2000 + b + p, 3000, 1500)
     d = _dev(c)
-    mf, st = ssj.ssj_self_join(d, p, q, b_bits=b, flags=SURV)
+    mf, st = ssj.ssj_self_join(d, p, q, b_bits=b, flags=SURV | MF)
     va, st2 = ssj.ssj_self_join(d, p, q, b_bits=b, flags=SURV | VALU)
     bm = oracle.bitmaps(c.offsets, c.tokens, b, oracle.BM_XOR)
     cnt, band, surv = oracle.survivors(c.offsets, bm, b, p, q, listing=True)
@@ -42,7 +46,7 @@ def test_self_join_survivors_equal_oracle_and_valu(b, pq):
     assert st["survivors"] == st2["survivors"] == cnt and st["band_pairs"] == band
     # and the join itself
     want = oracle.self_join(c.offsets, c.tokens, p, q)
-    got, _ = ssj.ssj_self_join(d, p, q, b_bits=b)
+    got, _ = ssj.ssj_self_join(d, p, q, b_bits=b, flags=MF)
     assert np.array_equal(got, want)
 
 
@@ -51,10 +55,10 @@ def test_rs_join_both_kernels(b):
     r, s = _coll(2100, 900, 1200), _coll(2101, 2500, 1200)
     for p, q in [(1, 2), (4, 5)]:
         want = oracle.rs_join(r.offsets, r.tokens, s.offsets, s.tokens, p, q)
-        for fl in (0, VALU):
+        for fl in (0, MF, VALU):
             got, _ = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=b, flags=fl)
             assert np.array_equal(got, want), (b, p, q, fl)
-        mf, _ = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=b, flags=SURV)
+        mf, _ = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=b, flags=SURV | MF)
         va, _ = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=b, flags=SURV | VALU)
         assert np.array_equal(mf, va), (b, p, q)
 
@@ -68,9 +72,9 @@ def test_other_functions_both_kernels(sim, osim):
     for p, q in pq:
         want = oracle.self_join(c.offsets, c.tokens, p, q, sim=osim)
         for b in (0, 128):
-            got, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim)
+            got, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=MF)
             assert np.array_equal(got, want), (sim, p, q, b)
-            mf, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV)
+            mf, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV | MF)
             va, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV | VALU)
             assert np.array_equal(mf, va), (sim, p, q, b)
 
@@ -83,15 +87,15 @@ def test_drains_resume_inside_steps(b):
     exactly once."""
     c = _coll(2300 + b, 5000, 400, hi=60, planted=0.5)
     d = _dev(c)
-    full, st0 = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=SURV)
+    full, st0 = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=SURV | MF)
     assert st0["filter_launches"] == 1 and len(full) > 50_000
-    small, st = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=SURV, queue_capacity=1)
+    small, st = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=SURV | MF, queue_capacity=1)
     assert st["filter_launches"] > 10
     assert np.array_equal(small, full)
     va, _ = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=SURV | VALU, queue_capacity=1)
     assert np.array_equal(va, full)
     want = oracle.self_join(c.offsets, c.tokens, 1, 3)
-    got, _ = ssj.ssj_self_join(d, 1, 3, b_bits=b, queue_capacity=1)
+    got, _ = ssj.ssj_self_join(d, 1, 3, b_bits=b, flags=MF, queue_capacity=1)
     assert np.array_equal(got, want)
 
 
@@ -99,7 +103,7 @@ def test_batch_and_index_both_kernels():
     cols = [_coll(2400 + k, n, 800) for k, n in enumerate((50, 700, 2000, 1))]
     pq = [(1, 2), (7, 10), (4, 5), (1, 2)]
     a, _ = ssj.ssj_self_join_batch([_dev(c) for c in cols], [p for p, _ in pq],
-                                   [q for _, q in pq], b_bits=0)
+                                   [q for _, q in pq], b_bits=0, flags=MF)
     b, _ = ssj.ssj_self_join_batch([_dev(c) for c in cols], [p for p, _ in pq],
                                    [q for _, q in pq], b_bits=0, flags=VALU)
     for c, (p, q), x, y in zip(cols, pq, a, b):
@@ -108,8 +112,23 @@ def test_batch_and_index_both_kernels():
     res = _coll(2500, 20_000, 3000)
     qs = [_coll(2501, 300, 3000), _coll(2502, 40, 3000)]
     with ssj.Index(_dev(res)) as idx:
-        for fl in (0, VALU):
+        for fl in (0, MF, VALU):
             got, _ = idx.query([_dev(x) for x in qs], [7, 1], [10, 2], flags=fl)
             for x, (p, q), g in zip(qs, [(7, 10), (1, 2)], got):
                 want = oracle.rs_join(x.offsets, x.tokens, res.offsets, res.tokens, p, q)
                 assert np.array_equal(g, want), fl
+
+
+def test_small_classes_take_the_vector_alus_and_flags_conflict():
+    """By default a width class below 2^26 band pairs runs on the vector
+    ALUs: the survivor set is the same either way, and SSJ_FLAG_MFMA with
+    SSJ_FLAG_VALU is rejected."""
+    c = _coll(2600, 3000, 1500)
+    d = _dev(c)
+    dflt, st = ssj.ssj_self_join(d, 1, 2, b_bits=0, flags=SURV)
+    mf, st_mf = ssj.ssj_self_join(d, 1, 2, b_bits=0, flags=SURV | MF)
+    assert st["band_pairs"] < 1 << 26
+    assert np.array_equal(dflt, mf) and st["survivors"] == st_mf["survivors"]
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_self_join(d, 1, 2, flags=MF | VALU)
+    assert e.value.status == ssj.SSJ_E_INVALID
