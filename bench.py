@@ -33,7 +33,7 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9   # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 G
 PEAK_FP4 = 10.1e15                # dense fp4 MFMA flop/s (published)
 PEAK_HBM = 8.0e12                 # bytes/s
 MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
-MFMA_MIN_BAND = 1 << 26           # ... for a width class of at least this many band pairs
+MFMA_MIN_BAND = 1 << 26           # ... and b = 256 only for a class of at least this many band pairs
 
 # HBM bytes per launch of the dominant filter launch (the b = 64 class of the
 # 1,000,000-set workload at 4/5, matrix-core kernel), from two rocprofv3
@@ -236,7 +236,7 @@ def roofline_of(stats_list, steps, valu=False):
     band = s0["class_ops"][dom] / (b // 16 + 1)  # band pairs of the class
     stage = {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
              "valu_equiv_frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}
-    if b in MFMA_BITS and not valu and band >= MFMA_MIN_BAND:
+    if b in MFMA_BITS and not valu and (b < 256 or band >= MFMA_MIN_BAND):
         achieved = band * 2 * b / (dom_ms / 1e3)
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP4 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP4, "traffic": None,

@@ -142,10 +142,10 @@ typedef struct {
 
 /* Run the bitmap filter on the vector ALUs at every width.  By default the
  * widths b = 64, 128 and 256 run on the matrix cores, which score the
- * Hamming distance of Theorem 1 as a dot product of +-1 vectors (exact),
- * for every width class of at least 2^26 band pairs; a smaller class runs
- * on the vector ALUs, whose launch costs less.  The two kernels keep the
- * same pairs.  Changes the work, never the result. */
+ * Hamming distance of Theorem 1 as a dot product of +-1 vectors (exact);
+ * a b = 256 class of fewer than 2^26 band pairs runs on the vector ALUs,
+ * whose launch costs less.  The two kernels keep the same pairs.  Changes
+ * the work, never the result. */
 #define SSJ_FLAG_VALU 4u
 
 /* Run the bitmap filter on the matrix cores at b = 64, 128 and 256 for

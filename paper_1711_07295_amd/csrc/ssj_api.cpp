@@ -42,11 +42,14 @@ constexpr uint32_t kDefaultTileCols = 2048;
 constexpr uint64_t kMinSlotTiles = 16384;
 constexpr uint32_t kMinTileCols = 64;
 constexpr uint32_t kMinTileColsValu = 32;
-// A width class of fewer band pairs than this runs on the vector ALUs even
-// where a matrix-core shape exists: the matrix-core launch has the larger
-// fixed cost (about 0.12 ms against 0.07 ms for a class of 1.6e6 pairs at
-// b = 256), and below this the fixed cost dominates.
+// A b = 256 class (four words) of fewer band pairs than this runs on the
+// vector ALUs: there the matrix-core launch has the larger fixed cost
+// (about 0.12 ms against 0.07 ms for a class of 1.6e6 pairs), and its sign
+// planes need not be built.  Narrower classes stay on the matrix cores at
+// any size: a query of a few sets against a large index sweeps long column
+// ranges, 32 columns a step there against a few on the vector ALUs.
 constexpr uint64_t kMfmaMinBand = 1ull << 26;
+constexpr uint32_t kMfmaMinBandWords = 4;
 constexpr uint64_t kMaxTable = 1ull << 26;       // largest |r| + |s| handled
 
 struct Fail {
@@ -905,9 +908,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     pl.n_slots = 1;
   }
   // band pairs of each slot, and its kernel: the matrix cores where the
-  // width has a matrix-core shape and the slot holds at least kMfmaMinBand
-  // band pairs (or the caller asked for them), else the vector ALUs, whose
-  // launch costs less
+  // width has a matrix-core shape, unless it is a small b = 256 class (see
+  // kMfmaMinBand) and the caller did not ask for them
   uint64_t slot_band[kMaxClasses] = {0, 0, 0, 0};
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     for (uint32_t t = 0; t < n_tasks; ++t) {
@@ -920,7 +922,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       }
     }
     pl.slot_mfma[k] = filter_shape(pl.slot_words[k], pl.mfma).mfma &&
-                      (jc.mfma_always || slot_band[k] >= kMfmaMinBand);
+                      (jc.mfma_always || pl.slot_words[k] < kMfmaMinBandWords ||
+                       slot_band[k] >= kMfmaMinBand);
   }
   // the widths to build: every class's, and in automatic mode the widest
   // automatic width for the cascade test of verification (same pass)

@@ -4,9 +4,9 @@ distance of Theorem 1 as a dot product of +-1 vectors, exact in fp32, so
 both kernels must keep exactly the same pairs: the survivor sets
 (SSJ_FLAG_SURVIVORS_ONLY) are compared whole, also through queue drains
 that resume inside a step.  These inputs are small, so SSJ_FLAG_MFMA puts
-every width class on the matrix cores (by default a class this small runs
-on the vector ALUs, whose launch costs less); one test also checks that
-default."""
+every width class on the matrix cores (by default a b = 256 class this
+small runs on the vector ALUs, whose launch costs less); one test also
+checks that default."""
 import numpy as np
 import pytest
 
@@ -120,13 +120,13 @@ def test_batch_and_index_both_kernels():
 
 
 def test_small_classes_take_the_vector_alus_and_flags_conflict():
-    """By default a width class below 2^26 band pairs runs on the vector
+    """By default a b = 256 class below 2^26 band pairs runs on the vector
     ALUs: the survivor set is the same either way, and SSJ_FLAG_MFMA with
     SSJ_FLAG_VALU is rejected."""
     c = _coll(2600, 3000, 1500)
     d = _dev(c)
-    dflt, st = ssj.ssj_self_join(d, 1, 2, b_bits=0, flags=SURV)
-    mf, st_mf = ssj.ssj_self_join(d, 1, 2, b_bits=0, flags=SURV | MF)
+    dflt, st = ssj.ssj_self_join(d, 1, 2, b_bits=256, flags=SURV)
+    mf, st_mf = ssj.ssj_self_join(d, 1, 2, b_bits=256, flags=SURV | MF)
     assert st["band_pairs"] < 1 << 26
     assert np.array_equal(dflt, mf) and st["survivors"] == st_mf["survivors"]
     with pytest.raises(ssj.SsjError) as e:
