@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 JACCARD, DICE, COSINE, OVERLAP = 0, 1, 2, 3
-BM_XOR, BM_SET, BM_NEXT = 0, 1, 2
+BM_XOR, BM_SET, BM_NEXT, BM_COMBINED = 0, 1, 2, 3
 
 _lib = None
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -64,8 +64,12 @@ def _load():
         lib.oracle_overlap_ub.restype = u64
         lib.oracle_bitmap_survives.argtypes = [u64, u64, u64, u64, u64]
         lib.oracle_bitmap_survives.restype = c_int
-        lib.oracle_survivors.argtypes = [vp, u64, vp, ctypes.c_uint32, vp, u64, u64, c_int, vp,
-                                         ctypes.POINTER(_u64p)]
+        lib.oracle_bitmap_survives_sim.argtypes = [c_int, u64, u64, u64, u64, u64]
+        lib.oracle_bitmap_survives_sim.restype = c_int
+        lib.oracle_combined_method.argtypes = [u64, u64]
+        lib.oracle_combined_method.restype = c_int
+        lib.oracle_survivors.argtypes = [vp, u64, vp, ctypes.c_uint32, vp, c_int, u64, u64, c_int,
+                                         vp, ctypes.POINTER(_u64p)]
         lib.oracle_survivors.restype = i64
         lib.oracle_check_pairs.argtypes = [vp, vp, vp, vp, vp, u64, c_int, u64, u64, vp]
         lib.oracle_check_pairs.restype = None
@@ -217,9 +221,26 @@ def band_pairs_rs(r_sizes, s_sizes, p: int, q: int, sim: int = JACCARD) -> int:
     return total
 
 
-def bitmap(tokens, b: int, method: int = BM_XOR) -> np.ndarray:
-    """One set's bitmap, b/64 uint64 words (Alg. 3/4/5, h(t) = t mod b)."""
+def combined_method(p: int, q: int) -> int:
+    """The generator Bitmap-Combined (Alg. 6) takes for a Jaccard threshold
+    t = p/q: Next, Set or Xor by the normalized threshold 2t/(1+t)."""
+    return int(_load().oracle_combined_method(p, q))
+
+
+def _method(method: int, p, q) -> int:
+    if method != BM_COMBINED:
+        return method
+    if not p or not q:
+        raise ValueError("Bitmap-Combined needs the threshold p/q")
+    return combined_method(p, q)
+
+
+def bitmap(tokens, b: int, method: int = BM_XOR, p: int | None = None,
+           q: int | None = None) -> np.ndarray:
+    """One set's bitmap, b/64 uint64 words (Alg. 3/4/5, h(t) = t mod b;
+    Alg. 6 with the Jaccard threshold p/q)."""
     lib = _load()
+    method = _method(method, p, q)
     t = np.ascontiguousarray(tokens, dtype=np.uint32)
     tb = t if t.size else np.zeros(1, dtype=np.uint32)
     out = np.zeros(b // 64, dtype=np.uint64)
@@ -229,9 +250,12 @@ def bitmap(tokens, b: int, method: int = BM_XOR) -> np.ndarray:
     return out
 
 
-def bitmaps(offsets, tokens, b: int, method: int = BM_XOR) -> np.ndarray:
-    """(N, b/64) uint64 bitmaps of every set, caller order."""
+def bitmaps(offsets, tokens, b: int, method: int = BM_XOR, p: int | None = None,
+            q: int | None = None) -> np.ndarray:
+    """(N, b/64) uint64 bitmaps of every set, caller order (Bitmap-Combined:
+    the generator Alg. 6 picks for the Jaccard threshold p/q)."""
     lib = _load()
+    method = _method(method, p, q)
     off, tok = _u64(offsets), _u32(tokens)
     n = off.shape[0] - 1
     out = np.zeros((max(n, 1), b // 64), dtype=np.uint64)
@@ -246,15 +270,18 @@ def overlap_ub(nr: int, ns: int, hamming: int) -> int:
     return int(_load().oracle_overlap_ub(nr, ns, hamming))
 
 
-def bitmap_survives(nr: int, ns: int, hamming: int, p: int, q: int) -> bool:
-    """Alg. 7's decision for a Jaccard threshold p/q: not pruned."""
-    return bool(_load().oracle_bitmap_survives(nr, ns, hamming, p, q))
+def bitmap_survives(nr: int, ns: int, hamming: int, p: int, q: int, sim: int | None = None) -> bool:
+    """Alg. 7's decision for a threshold p/q: not pruned.  Without ``sim``
+    the Jaccard-only form; with it, the form for any function of Table 1."""
+    if sim is None:
+        return bool(_load().oracle_bitmap_survives(nr, ns, hamming, p, q))
+    return bool(_load().oracle_bitmap_survives_sim(sim, nr, ns, hamming, p, q))
 
 
 def survivors(offsets, bms, b: int, p: int, q: int, order=None, listing: bool = False,
-              threads: int | None = None):
-    """Survivors of the bitmap filter over the Jaccard length band.
-    Returns (count, band_pairs, pairs or None)."""
+              threads: int | None = None, sim: int = JACCARD):
+    """Survivors of the bitmap filter over the length band of the function
+    ``sim``.  Returns (count, band_pairs, pairs or None)."""
     lib = _load()
     off = _u64(offsets)
     n = off.shape[0] - 1
@@ -266,8 +293,8 @@ def survivors(offsets, bms, b: int, p: int, q: int, order=None, listing: bool = 
     order = _u32(order)
     band = ctypes.c_uint64()
     ptr = _u64p()
-    cnt = lib.oracle_survivors(off.ctypes.data, n, bm.ctypes.data, b, order.ctypes.data, p, q,
-                               _threads(threads), ctypes.byref(band),
+    cnt = lib.oracle_survivors(off.ctypes.data, n, bm.ctypes.data, b, order.ctypes.data, sim, p,
+                               q, _threads(threads), ctypes.byref(band),
                                ctypes.byref(ptr) if listing else None)
     if cnt < 0:
         raise MemoryError("oracle failed")

@@ -27,7 +27,7 @@
 #include <string.h>
 
 enum { SIM_JACCARD = 0, SIM_DICE = 1, SIM_COSINE = 2, SIM_OVERLAP = 3 };
-enum { BM_XOR = 0, BM_SET = 1, BM_NEXT = 2 };
+enum { BM_XOR = 0, BM_SET = 1, BM_NEXT = 2, BM_COMBINED = 3 };
 
 /* ------------------------------------------------------------------ */
 /* Overlap and union of two sorted sets by one two-pointer pass; both are
@@ -312,6 +312,20 @@ uint64_t oracle_band_pairs(const uint64_t *hist, uint64_t max_size, int sim, uin
 }
 
 /* ------------------------------------------------------------------ */
+/* Bitmap-Combined (Alg. 6, Section 3.5): Bitmap-Next when tau <= 0.56,
+ * Bitmap-Xor when tau >= 0.73, Bitmap-Set in between.  tau is on the scale of
+ * the cutoff analysis (Section 3.4): the overlap fraction two sets of n tokens
+ * need, which for a Jaccard threshold t = p/q is 2t / (1 + t) = 2p / (p + q)
+ * (Table 1 with |r| = |s| = n).  Decided in integers:
+ *   2p/(p+q) <= 56/100  <=>  200 p <= 56 (p + q)
+ *   2p/(p+q) >= 73/100  <=>  200 p >= 73 (p + q)                        */
+int oracle_combined_method(uint64_t p, uint64_t q) {
+  if (200 * p <= 56 * (p + q)) return BM_NEXT;
+  if (200 * p >= 73 * (p + q)) return BM_XOR;
+  return BM_SET;
+}
+
+/* ------------------------------------------------------------------ */
 /* Bitmap generation (Section 3.2) with h(t) = t mod b.
  *   Bitmap-Set (Alg. 3): set bit h(t) for every token.
  *   Bitmap-Xor (Alg. 4): flip bit h(t) for every token.
@@ -379,9 +393,33 @@ int oracle_bitmap_survives(uint64_t nr, uint64_t ns, uint64_t hamming, uint64_t 
   return !((p + q) * ub < p * (nr + ns));
 }
 
+/* Alg. 7's decision for any function of Table 1: the pair is pruned when
+ * the upper bound of Eq. 2 is below the overlap the threshold t = p/q
+ * requires (Table 1's overlap column):
+ *   Jaccard  UB < t/(1+t) (|r|+|s|)   <=>  (p+q) UB < p (|r|+|s|)
+ *   Dice     UB < t/2 (|r|+|s|)       <=>  2q UB < p (|r|+|s|)
+ *   Cosine   UB < t sqrt(|r| |s|)     <=>  q^2 UB^2 < p^2 |r| |s|   (UB >= 0)
+ *   Overlap  UB < t                   <=>  q UB < p
+ * Returns 1 when the pair survives. */
+int oracle_bitmap_survives_sim(int sim, uint64_t nr, uint64_t ns, uint64_t hamming, uint64_t p,
+                               uint64_t q) {
+  uint64_t ub = oracle_overlap_ub(nr, ns, hamming);
+  switch (sim) {
+    case SIM_JACCARD: return !((p + q) * ub < p * (nr + ns));
+    case SIM_DICE: return !(2 * q * ub < p * (nr + ns));
+    case SIM_COSINE: {
+      unsigned __int128 lhs = (unsigned __int128)(q * ub) * (q * ub);
+      unsigned __int128 rhs = (unsigned __int128)(p * p) * ((unsigned __int128)nr * ns);
+      return !(lhs < rhs);
+    }
+    case SIM_OVERLAP: return !(q * ub < p);
+    default: return 1;
+  }
+}
+
 typedef struct {
   const uint64_t *off; const uint64_t *bm; uint32_t W;
-  const uint32_t *order; uint64_t n; uint64_t p, q;
+  const uint32_t *order; uint64_t n; uint64_t p, q; int sim;
   uint64_t next;
   uint64_t *surv;   /* per thread */
   uint64_t *band;   /* per thread */
@@ -403,10 +441,10 @@ static void *surv_worker(void *vp) {
       if (ni == 0) continue;
       for (uint64_t y = x; y-- > 0;) {
         uint64_t j = J->order[y], nj = set_len(J->off, j);
-        if (nj == 0 || !oracle_length_ok(SIM_JACCARD, ni, nj, J->p, J->q)) break;
+        if (nj == 0 || !oracle_length_ok(J->sim, ni, nj, J->p, J->q)) break;
         ++bd;
         uint64_t h = popcount_words(J->bm + i * J->W, J->bm + j * J->W, J->W);
-        if (oracle_bitmap_survives(ni, nj, h, J->p, J->q)) {
+        if (oracle_bitmap_survives_sim(J->sim, ni, nj, h, J->p, J->q)) {
           ++sv;
           if (J->list) {
             uint64_t lo = i < j ? i : j, hi = i < j ? j : i;
@@ -421,19 +459,21 @@ static void *surv_worker(void *vp) {
   return NULL;
 }
 
-/* Survivors of the bitmap filter over the length band of a Jaccard
- * self-join (Alg. 8: length filter, then the bitmap filter on every band
- * pair).  Bitmaps are given (from oracle_bitmaps).  Returns the survivor
- * count; *band_out gets the band size; when pairs_out is non-NULL the
- * survivors are listed as caller (min << 32 | max), ascending. */
+/* Survivors of the bitmap filter over the length band of a self-join with
+ * any function of Table 1 (Alg. 8: length filter of Table 2, then the bitmap
+ * filter of Alg. 7 on every band pair).  Bitmaps are given (from
+ * oracle_bitmaps).  Returns the survivor count; *band_out gets the band size;
+ * when pairs_out is non-NULL the survivors are listed as caller
+ * (min << 32 | max), ascending. */
 int64_t oracle_survivors(const uint64_t *offsets, uint64_t n, const uint64_t *bitmaps, uint32_t b,
-                         const uint32_t *order, uint64_t p, uint64_t q, int nthreads,
+                         const uint32_t *order, int sim, uint64_t p, uint64_t q, int nthreads,
                          uint64_t *band_out, uint64_t **pairs_out) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   surv_job J;
   memset(&J, 0, sizeof(J));
   J.off = offsets; J.bm = bitmaps; J.W = b / 64; J.order = order; J.n = n; J.p = p; J.q = q;
+  J.sim = sim;
   J.list = pairs_out != NULL;
   J.surv = (uint64_t *)calloc(nthreads, sizeof(uint64_t));
   J.band = (uint64_t *)calloc(nthreads, sizeof(uint64_t));
