@@ -1,6 +1,6 @@
 /*
  * ssj.h -- exact set similarity join with the Bitmap Filter on one AMD
- * Instinct MI355X (gfx950).  C ABI, version 1.
+ * Instinct MI355X (gfx950).  C ABI, version 2.
  *
  * Method: Sandes, Teodoro, Melo, "Bitmap Filter: Speeding up Exact Set
  * Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SSJ_ABI_VERSION 1
+#define SSJ_ABI_VERSION 2
 
 typedef enum {
   SSJ_OK = 0,
@@ -74,12 +74,23 @@ typedef enum {
 } ssj_sim;
 
 /* Bitmap generators of Section 3.2: Bitmap-Xor (Alg. 4), Bitmap-Set
- * (Alg. 3), Bitmap-Next (Alg. 5).  Theorem 1 holds for all three; the
- * join treats any of them alike. */
+ * (Alg. 3), Bitmap-Next (Alg. 5), and Bitmap-Combined (Alg. 6,
+ * Section 3.5), which takes one of the three by the threshold the bitmaps
+ * are used at.  Theorem 1 holds for all of them; the join treats any of them
+ * alike.
+ *
+ * Bitmap-Combined's choice.  The paper states its ranges on the scale of
+ * the cutoff analysis (Section 3.4): the overlap fraction tau two sets of n
+ * tokens need to be similar, which is 2t / (1 + t) for a Jaccard threshold
+ * t (Table 1 with |r| = |s|), and t itself for Dice and Cosine.  On that
+ * scale the cutoff curves of Eqs. 4-6 cross where the paper puts the
+ * ranges: Bitmap-Next when tau <= 0.56, Bitmap-Xor when tau >= 0.73,
+ * Bitmap-Set in between.  Compared exactly, in integers. */
 typedef enum {
   SSJ_BM_XOR = 0,
   SSJ_BM_SET = 1,
-  SSJ_BM_NEXT = 2
+  SSJ_BM_NEXT = 2,
+  SSJ_BM_COMBINED = 3
 } ssj_bm_method;
 
 typedef struct {
@@ -133,7 +144,7 @@ typedef struct {
  * survivor set (caller indices), not the join. */
 #define SSJ_FLAG_SURVIVORS_ONLY 1u
 
-/* Apply the bitmap filter only to rows up to the cutoff point (Section 3.4,
+/* Apply the bitmap filter only to rows up to the cutoff point (Section 3.5,
  * as Alg. 7 does; see ssj_cutoff) of their widest width; rows of larger
  * sets take their candidates from an index of set prefixes (the prefix
  * filter) instead.  Changes the work, never the result.  With
@@ -154,21 +165,27 @@ typedef struct {
 #define SSJ_FLAG_MFMA 8u
 
 /*
- * ssj_build_bitmaps -- the bitmap of every set (Section 3.2, Alg. 3/4/5,
+ * ssj_build_bitmaps -- the bitmap of every set (Section 3.2, Alg. 3/4/5/6,
  * precomputed once as in the initialization of Alg. 7).
  *   s            collection (device CSR), validated as above
  *   b_bits       bitmap width b: multiple of 64 in [64, 4096]
  *   method       ssj_bm_method
+ *   p, q         read only by SSJ_BM_COMBINED: the Jaccard threshold t = p/q
+ *                the bitmaps will be joined at, 1 <= p <= q (reduced
+ *                internally); Alg. 6 then builds Next, Set or Xor by
+ *                2t/(1+t).  (For a Dice or Cosine threshold t', pass the
+ *                Jaccard threshold with the same normalized value,
+ *                t'/(2 - t'); ssj_cutoff resolves Combined per function.)
  *   bitmaps_dev  caller-owned device buffer of n_sets * b_bits / 64 uint64,
  *                written in caller order
  *   hip_stream   stream for the work; the call returns after the stream
  *                is synchronised (validation result is needed)
- * Errors: SSJ_E_INVALID (null pointer, bad b, bad offsets),
- *         SSJ_E_UNSORTED, SSJ_E_UNSUPPORTED (unknown method),
- *         SSJ_E_NOMEM, SSJ_E_DEVICE.
+ * Errors: SSJ_E_INVALID (null pointer, bad b, bad offsets, Combined with a
+ *         bad threshold), SSJ_E_UNSORTED, SSJ_E_UNSUPPORTED (unknown
+ *         method), SSJ_E_NOMEM, SSJ_E_DEVICE.
  */
-int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *bitmaps_dev,
-                      void *hip_stream);
+int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p, uint32_t q,
+                      uint64_t *bitmaps_dev, void *hip_stream);
 
 /*
  * ssj_self_join -- every pair (i, j), i < j (caller indices), with
@@ -284,15 +301,17 @@ int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
 void ssj_index_destroy(ssj_index *idx);
 
 /*
- * ssj_cutoff -- the cutoff point omega(b, t) of Section 3.4: the largest set
+ * ssj_cutoff -- the cutoff point omega(b, t) of Section 3.5: the largest set
  * size n for which the expected normalized overlap bound of two sets of n
- * random tokens, E(b, n) / n (Eq. 4 Bitmap-Set, Eq. 5 Bitmap-Xor, Eq. 6
- * Bitmap-Next), is at most the overlap fraction two n-sets need to reach the
- * threshold (Jaccard 2t/(1+t); Dice and Cosine t).  Alg. 7 applies the
- * bitmap filter to sets up to this size; beyond it the filter can no longer
- * tell most dissimilar pairs apart.  Host computation only.
+ * random tokens, E(b, n) / n (Section 3.4: Eq. 4 Bitmap-Set, Eq. 5
+ * Bitmap-Xor, Eq. 6 Bitmap-Next), is at most the overlap fraction two n-sets
+ * need to reach the threshold (Jaccard 2t/(1+t); Dice and Cosine t).  Alg. 7
+ * applies the bitmap filter to sets up to this size; beyond it the filter
+ * can no longer tell most dissimilar pairs apart.  Host computation only.
  *   b_bits       bitmap width, as ssj_build_bitmaps
- *   method       ssj_bm_method
+ *   method       ssj_bm_method; SSJ_BM_COMBINED: the cutoff of the generator
+ *                Alg. 6 picks for this function's normalized threshold (the
+ *                combined curve the paper precomputes for Alg. 7)
  *   sim, p, q    similarity function and threshold, as ssj_self_join
  *   out          receives omega; UINT32_MAX for SSJ_SIM_OVERLAP (an absolute
  *                threshold: never cut off); 0 on error

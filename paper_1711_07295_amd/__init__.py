@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libssj.so")
 SSJ_OK, SSJ_E_INVALID, SSJ_E_UNSORTED, SSJ_E_NOMEM, SSJ_E_DEVICE, SSJ_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 SSJ_SIM_JACCARD, SSJ_SIM_DICE, SSJ_SIM_COSINE, SSJ_SIM_OVERLAP = 0, 1, 2, 3
-SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT = 0, 1, 2
+SSJ_BM_XOR, SSJ_BM_SET, SSJ_BM_NEXT, SSJ_BM_COMBINED = 0, 1, 2, 3
 SSJ_FLAG_SURVIVORS_ONLY = 1
 SSJ_FLAG_CUTOFF = 2
 SSJ_FLAG_VALU = 4
@@ -89,7 +89,7 @@ def load() -> ctypes.CDLL:
         lib = ctypes.CDLL(LIB_PATH)
         vp, u32, u64, c_int = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
         sp = ctypes.POINTER(ssj_sets)
-        lib.ssj_build_bitmaps.argtypes = [sp, u32, c_int, vp, vp]
+        lib.ssj_build_bitmaps.argtypes = [sp, u32, c_int, u32, u32, vp, vp]
         lib.ssj_build_bitmaps.restype = c_int
         lib.ssj_self_join.argtypes = [sp, vp, u32, c_int, u32, u32, ctypes.POINTER(ssj_options),
                                       ctypes.POINTER(ssj_pairs), ctypes.POINTER(ssj_stats), vp]
@@ -191,15 +191,17 @@ def _opts(queue_capacity=0, tile_cols=0, flags=0):
     return ssj_options(queue_capacity, tile_cols, flags)
 
 
-def ssj_build_bitmaps(sets: DeviceSets, b_bits: int, method: int = SSJ_BM_XOR, out=None,
-                      stream=None):
-    """Bitmaps of every set (caller order) as a (N, b/64) int64 tensor."""
+def ssj_build_bitmaps(sets: DeviceSets, b_bits: int, method: int = SSJ_BM_XOR, p: int = 0,
+                      q: int = 0, out=None, stream=None):
+    """Bitmaps of every set (caller order) as a (N, b/64) int64 tensor.
+    ``p, q``: the Jaccard threshold Bitmap-Combined chooses its generator by
+    (read only for SSJ_BM_COMBINED)."""
     import torch
     if out is None:
         out = torch.empty((sets.n_sets, b_bits // 64), dtype=torch.int64,
                           device=sets.offsets.device)
     cs = sets.c()
-    st = load().ssj_build_bitmaps(ctypes.byref(cs), b_bits, method,
+    st = load().ssj_build_bitmaps(ctypes.byref(cs), b_bits, method, p, q,
                                   out.data_ptr() if out.numel() else None, _stream(stream))
     if st != SSJ_OK:
         raise SsjError(st, "ssj_build_bitmaps")
@@ -318,7 +320,7 @@ class Index:
 
 def ssj_cutoff(b_bits: int, p: int, q: int, method: int = SSJ_BM_XOR,
                sim: int = SSJ_SIM_JACCARD) -> int:
-    """The cutoff point omega(b, p/q) of Section 3.4 (host computation)."""
+    """The cutoff point omega(b, p/q) of Section 3.5 (host computation)."""
     out = ctypes.c_uint32()
     st = load().ssj_cutoff(b_bits, method, sim, p, q, ctypes.byref(out))
     if st != SSJ_OK:

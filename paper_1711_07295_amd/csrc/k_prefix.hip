@@ -1,5 +1,5 @@
 // Prefix-filtered candidate generation for the rows past the cutoff point
-// (Section 3.4): rows whose sets are too large for their bitmaps to tell
+// (Section 3.5): rows whose sets are too large for their bitmaps to tell
 // dissimilar pairs apart skip the bitmap filter (Alg. 7 applies it only up
 // to the cutoff) and take their candidates from an inverted index of set
 // prefixes instead (the prefix filter of Section 2.3).

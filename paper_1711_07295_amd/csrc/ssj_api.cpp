@@ -579,7 +579,8 @@ std::vector<WidthClass> choose_classes(uint32_t max_rows, int sim, uint64_t p, u
 }
 
 // ------------------------------------------------------------ cutoff point
-// E(b, n) of Section 3.4 for two sets of n random tokens (Eqs. 4-6) in
+// The cutoff point of Section 3.5 rests on E(b, n) of Section 3.4, the
+// expected bound of two sets of n random tokens (Eqs. 4-6), here in
 // closed form: Eq. 5's sum over odd k is the odd half of a binomial
 // expansion, (1 - (1 - 2/b)^(2n)) / 2, so E = n - (b/4)(1 - (1 - 2/b)^(2n)).
 // The overlap fraction o/n two n-sets need for sim >= p/q, as P/Q: Jaccard
@@ -622,12 +623,23 @@ bool bound_within(int method, uint64_t b, uint64_t n, uint64_t P, uint64_t Q) {
   }
 }
 
+// Bitmap-Combined (Alg. 6, Section 3.5) for a normalized threshold P/Q:
+// Bitmap-Next when P/Q <= 14/25 (0.56), Bitmap-Xor when P/Q >= 73/100,
+// Bitmap-Set in between.
+int combined_generator(uint64_t P, uint64_t Q) {
+  if (25 * P <= 14 * Q) return SSJ_BM_NEXT;
+  if (100 * P >= 73 * Q) return SSJ_BM_XOR;
+  return SSJ_BM_SET;
+}
+
 // The largest n with E(b, n)/n <= tau (E/n grows with n), up to 2^20; the
 // filter is applied to sets up to this size (Alg. 7).  UINT32_MAX: never
-// cut off (Overlap).
+// cut off (Overlap).  Bitmap-Combined takes the curve of the generator it
+// picks for tau.
 uint32_t cutoff_point(int method, uint32_t b, int sim, uint64_t p, uint64_t q) {
   uint64_t P = 0, Q = 1;
   if (!normalized_threshold(sim, p, q, P, Q)) return 0xFFFFFFFFu;
+  if (method == SSJ_BM_COMBINED) method = combined_generator(P, Q);
   auto ok = [&](uint64_t n) { return bound_within(method, b, n, P, Q); };
   if (!ok(1)) return 0;
   uint64_t lo = 1, hi = 1ull << 20;
@@ -866,7 +878,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       classes[k] = choose_classes(std::max<uint32_t>(a_max, 1), tk.sim, tk.p, tk.q);
     else classes[k].push_back({a_max, wpad});
   }
-  // The cutoff point (Section 3.4) of every task at its widest width: rows
+  // The cutoff point (Section 3.5) of every task at its widest width: rows
   // of larger sets skip the bitmap filter and take prefix-filtered
   // candidates instead.
   std::vector<uint32_t> omega(n_tasks, 0xFFFFFFFFu);
@@ -1502,13 +1514,20 @@ const char *ssj_status_string(int status) {
   }
 }
 
-int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *bitmaps_dev,
-                      void *hip_stream) {
+int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p, uint32_t q,
+                      uint64_t *bitmaps_dev, void *hip_stream) {
   using namespace ssj;
   try {
     validate_sets(s);
     if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
-    if (method < SSJ_BM_XOR || method > SSJ_BM_NEXT) return SSJ_E_UNSUPPORTED;
+    if (method < SSJ_BM_XOR || method > SSJ_BM_COMBINED) return SSJ_E_UNSUPPORTED;
+    if (method == SSJ_BM_COMBINED) {
+      // Alg. 6 by the normalized value 2t/(1+t) of the Jaccard threshold
+      check_threshold(SSJ_SIM_JACCARD, p, q);
+      uint64_t P = 0, Q = 1;
+      normalized_threshold(SSJ_SIM_JACCARD, p, q, P, Q);
+      method = combined_generator(P, Q);
+    }
     if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Arena ar(st);
@@ -1643,7 +1662,7 @@ int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uin
   if (!out) return SSJ_E_INVALID;
   *out = 0;
   if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
-  if (method < SSJ_BM_XOR || method > SSJ_BM_NEXT) return SSJ_E_UNSUPPORTED;
+  if (method < SSJ_BM_XOR || method > SSJ_BM_COMBINED) return SSJ_E_UNSUPPORTED;
   try {
     check_threshold(sim, p, q);
   } catch (const Fail &f) {

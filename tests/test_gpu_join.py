@@ -36,6 +36,36 @@ def test_bitmaps_match_oracle(method, b):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("pq", [(1, 5), (7, 18), (1, 2), (73, 127), (4, 5)])
+@pytest.mark.parametrize("b", [64, 192, 4096])
+def test_combined_bitmaps_match_oracle(pq, b):
+    """Bitmap-Combined (Alg. 6): the generator picked by the threshold,
+    bit-exact against the oracle's Combined, on both sides of the printed
+    range edges (7/18 and 73/127 sit exactly on 0.56 and 0.73)."""
+    p, q = pq
+    c = gen.generate(n_sets=2000, universe=20000, zipf_s=0.9, size_dist=gen.SIZE_LOGNORMAL,
+                     size_a=40.0, size_b=1.0, size_lo=0, size_hi=5000, seed=b + p)
+    got = _bm_np(ssj.ssj_build_bitmaps(_dev(c), b, ssj.SSJ_BM_COMBINED, p, q))
+    want = oracle.bitmaps(c.offsets, c.tokens, b, oracle.BM_COMBINED, p, q)
+    assert np.array_equal(got, want)
+
+
+def test_combined_bitmaps_join_unchanged_and_bad_threshold():
+    c = _ragged(77)
+    d = _dev(c)
+    for p, q in ((1, 2), (4, 5)):
+        bm = ssj.ssj_build_bitmaps(d, 128, ssj.SSJ_BM_COMBINED, p, q)
+        got, _ = ssj.ssj_self_join(d, p, q, b_bits=128, bitmaps=bm)
+        assert np.array_equal(got, oracle.self_join(c.offsets, c.tokens, p, q))
+    for p, q in ((0, 1), (3, 2), (1, 0)):
+        with pytest.raises(ssj.SsjError) as e:
+            ssj.ssj_build_bitmaps(d, 64, ssj.SSJ_BM_COMBINED, p, q)
+        assert e.value.status == ssj.SSJ_E_INVALID
+    with pytest.raises(ssj.SsjError) as e:
+        ssj.ssj_build_bitmaps(d, 64, 4)
+    assert e.value.status == ssj.SSJ_E_UNSUPPORTED
+
+
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("pq", [(1, 2), (7, 10), (4, 5), (9, 10), (1, 1)])
 def test_self_join_matches_oracle(seed, pq):

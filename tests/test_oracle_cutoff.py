@@ -86,6 +86,19 @@ def test_library_cutoff_matches_oracle(b):
                 assert st == ssj.SSJ_OK
                 want = oracle.cutoff(om, b, oracle.normalized_threshold(osim, p, q))
                 assert got == want, (b, method, sim, p, q, got, want)
+    # Bitmap-Combined: the cutoff of the generator Alg. 6 picks for the
+    # function's normalized threshold (for Dice and Cosine t, which is the
+    # normalized value of the Jaccard threshold t / (2 - t))
+    from fractions import Fraction
+    for sim, osim in ((ssj.SSJ_SIM_JACCARD, oracle.JACCARD), (ssj.SSJ_SIM_DICE, oracle.DICE),
+                      (ssj.SSJ_SIM_COSINE, oracle.COSINE)):
+        for p, q in ((1, 5), (1, 3), (1, 2), (3, 5), (7, 10), (4, 5), (9, 10)):
+            tau = oracle.normalized_threshold(osim, p, q)
+            tj = tau / (2 - tau)
+            om = oracle.combined_method(tj.numerator, tj.denominator)
+            st, got = _lib_cutoff(b, ssj.SSJ_BM_COMBINED, sim, p, q)
+            assert st == ssj.SSJ_OK and got == oracle.cutoff(om, b, tau), (b, sim, p, q)
+            assert 2 * tj / (1 + tj) == tau and isinstance(tj, Fraction)
     # Overlap has no normalized threshold: the filter is never cut off
     st, got = _lib_cutoff(b, ssj.SSJ_BM_XOR, ssj.SSJ_SIM_OVERLAP, 3, 1)
     assert st == ssj.SSJ_OK and got == 0xFFFFFFFF
