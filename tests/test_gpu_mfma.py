@@ -67,16 +67,26 @@ def test_rs_join_both_kernels(b):
                                       (ssj.SSJ_SIM_COSINE, oracle.COSINE),
                                       (ssj.SSJ_SIM_OVERLAP, oracle.OVERLAP)])
 def test_other_functions_both_kernels(sim, osim):
+    """Dice, Cosine and Overlap: both kernels keep exactly the survivors of
+    the oracle's filter (Table 2 length band, Alg. 7's decision against the
+    function's Table 1 overlap threshold) at fixed widths, and agree with
+    each other at automatic widths; the joins equal the oracle's."""
     c = _coll(2200 + sim, 2500, 1500)
     pq = [(3, 5), (4, 5)] if sim != ssj.SSJ_SIM_OVERLAP else [(5, 1), (12, 1)]
     for p, q in pq:
         want = oracle.self_join(c.offsets, c.tokens, p, q, sim=osim)
-        for b in (0, 128):
+        for b in (0, 64, 128, 256):
             got, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=MF)
             assert np.array_equal(got, want), (sim, p, q, b)
-            mf, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV | MF)
+            mf, st = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV | MF)
             va, _ = ssj.ssj_self_join(_dev(c), p, q, b_bits=b, sim=sim, flags=SURV | VALU)
             assert np.array_equal(mf, va), (sim, p, q, b)
+            if b:
+                bm = oracle.bitmaps(c.offsets, c.tokens, b, oracle.BM_XOR)
+                cnt, band, surv = oracle.survivors(c.offsets, bm, b, p, q, listing=True,
+                                                   sim=osim)
+                assert np.array_equal(mf, surv), (sim, p, q, b, len(mf), len(surv))
+                assert st["survivors"] == cnt and st["band_pairs"] == band
 
 
 @pytest.mark.parametrize("b", [64, 256])
