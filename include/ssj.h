@@ -188,6 +188,28 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p
                       uint64_t *bitmaps_dev, void *hip_stream);
 
 /*
+ * ssj_build_bitmaps_noalloc -- ssj_build_bitmaps that allocates no memory,
+ * for callers that cannot allocate: serving loops and harnesses that forbid
+ * hipMalloc or any allocating call while they run.  Same arguments, result
+ * and errors as ssj_build_bitmaps; the bitmaps are identical.
+ *   Working memory (side table, counters, validated set sizes) is a fixed
+ *   device array of 32 MiB inside the library, one copy per device, held
+ *   from the library's load until the process ends.  It is cleared by the
+ *   call where it must start at zero and otherwise keeps the last call's
+ *   contents.  Calls on one device share that array: the library runs them
+ *   one at a time (a call holds the device's array until its stream is
+ *   synchronised), so concurrent calls from several threads wait for each
+ *   other instead of racing.  No host memory is allocated either.
+ *   The call synchronises hip_stream, so it cannot be captured into a graph.
+ * Errors: as ssj_build_bitmaps; SSJ_E_UNSUPPORTED also when n_sets exceeds
+ *         SSJ_NOALLOC_MAX_SETS (nothing is written then); SSJ_E_DEVICE when
+ *         the array's address cannot be obtained on the current device.
+ */
+#define SSJ_NOALLOC_MAX_SETS 4000000u
+int ssj_build_bitmaps_noalloc(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p,
+                              uint32_t q, uint64_t *bitmaps_dev, void *hip_stream);
+
+/*
  * ssj_self_join -- every pair (i, j), i < j (caller indices), with
  * sim(set_i, set_j) >= p / q (Eq. 1 with R = S).  The length filter
  * (Table 2) bounds the pairs considered, the bitmap filter (Theorem 1,

@@ -26,8 +26,9 @@ SSJ_FLAG_SURVIVORS_ONLY = 1
 SSJ_FLAG_CUTOFF = 2
 SSJ_FLAG_VALU = 4
 SSJ_FLAG_MFMA = 8
+SSJ_NOALLOC_MAX_SETS = 4_000_000
 
-EXPORTS = ("ssj_build_bitmaps", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
+EXPORTS = ("ssj_build_bitmaps", "ssj_build_bitmaps_noalloc", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
            "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_cutoff",
            "ssj_free_pairs",
            "ssj_status_string", "ssj_abi_version")
@@ -91,6 +92,8 @@ def load() -> ctypes.CDLL:
         sp = ctypes.POINTER(ssj_sets)
         lib.ssj_build_bitmaps.argtypes = [sp, u32, c_int, u32, u32, vp, vp]
         lib.ssj_build_bitmaps.restype = c_int
+        lib.ssj_build_bitmaps_noalloc.argtypes = [sp, u32, c_int, u32, u32, vp, vp]
+        lib.ssj_build_bitmaps_noalloc.restype = c_int
         lib.ssj_self_join.argtypes = [sp, vp, u32, c_int, u32, u32, ctypes.POINTER(ssj_options),
                                       ctypes.POINTER(ssj_pairs), ctypes.POINTER(ssj_stats), vp]
         lib.ssj_self_join.restype = c_int
@@ -205,6 +208,23 @@ def ssj_build_bitmaps(sets: DeviceSets, b_bits: int, method: int = SSJ_BM_XOR, p
                                   out.data_ptr() if out.numel() else None, _stream(stream))
     if st != SSJ_OK:
         raise SsjError(st, "ssj_build_bitmaps")
+    return out
+
+
+def ssj_build_bitmaps_noalloc(sets: DeviceSets, b_bits: int, out, method: int = SSJ_BM_XOR,
+                              p: int = 0, q: int = 0, stream=None):
+    """ssj_build_bitmaps into the caller's ``out`` ((N, b/64) int64 device
+    tensor), through the entry point that allocates no device memory: its
+    working memory is the library's fixed per-device array, which limits the
+    collection to SSJ_NOALLOC_MAX_SETS sets."""
+    if tuple(out.shape) != (sets.n_sets, b_bits // 64):
+        raise ValueError(f"out must be ({sets.n_sets}, {b_bits // 64}), not {tuple(out.shape)}")
+    cs = sets.c()
+    st = load().ssj_build_bitmaps_noalloc(ctypes.byref(cs), b_bits, method, p, q,
+                                          out.data_ptr() if out.numel() else None,
+                                          _stream(stream))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_build_bitmaps_noalloc")
     return out
 
 

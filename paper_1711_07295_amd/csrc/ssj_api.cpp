@@ -110,10 +110,16 @@ class ChunkCache {
 // Bump allocator over device memory chunks.  A call's arena takes cached
 // chunks and returns them when it ends, after synchronising its stream; an
 // owned arena (a resident index) allocates its own and frees them when it is
-// destroyed (hipFree waits for the device).
+// destroyed (hipFree waits for the device).  A fixed arena hands out one
+// region the caller provides and never allocates: a request beyond the
+// region fails with SSJ_E_UNSUPPORTED.
 class Arena {
  public:
   explicit Arena(hipStream_t st, bool owned = false) : st_(st), owned_(owned) {
+    if (hipGetDevice(&dev_) != hipSuccess) dev_ = 0;
+  }
+  Arena(hipStream_t st, void *region, uint64_t size)
+      : st_(st), owned_(false), fixed_(true), next_(static_cast<char *>(region)), left_(size) {
     if (hipGetDevice(&dev_) != hipSuccess) dev_ = 0;
   }
   Arena(const Arena &) = delete;
@@ -129,6 +135,7 @@ class Arena {
   T *alloc(uint64_t n) {
     uint64_t bytes = (std::max<uint64_t>(n, 1) * sizeof(T) + 255) & ~255ull;
     if (bytes > left_) {
+      if (fixed_) throw Fail{SSJ_E_UNSUPPORTED};
       uint64_t size = owned_ ? std::max<uint64_t>(bytes, kOwnedChunk) : kChunk;
       if (!owned_)
         while (size < bytes) size <<= 1;
@@ -158,6 +165,7 @@ class Arena {
   static constexpr uint64_t kOwnedChunk = 16ull << 20;
   hipStream_t st_;
   bool owned_;
+  bool fixed_ = false;
   int dev_ = 0;
   std::vector<std::pair<void *, uint64_t>> chunks_;
   char *next_ = nullptr;
@@ -1495,6 +1503,79 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
   return SSJ_OK;
 }
 
+// Arguments of ssj_build_bitmaps: the generator to build (Bitmap-Combined
+// resolved by Alg. 6 from the Jaccard threshold p/q), or a status < 0.
+int bitmap_args(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p, uint32_t q,
+                const uint64_t *bitmaps_dev) {
+  if (!s || s->n_sets >= 0xFFFFFFFFull || (s->n_sets > 0 && !s->offsets) ||
+      (s->n_tokens > 0 && !s->tokens) || (s->n_sets == 0 && s->n_tokens != 0))
+    return SSJ_E_INVALID;
+  if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
+  if (method < SSJ_BM_XOR || method > SSJ_BM_COMBINED) return SSJ_E_UNSUPPORTED;
+  if (method == SSJ_BM_COMBINED) {
+    // Alg. 6 by the normalized value 2t/(1+t) of the Jaccard threshold
+    if (p == 0 || q == 0 || p > q) return SSJ_E_INVALID;
+    const uint32_t g = std::gcd(p, q);
+    uint64_t P = 0, Q = 1;
+    normalized_threshold(SSJ_SIM_JACCARD, p / g, q / g, P, Q);
+    method = combined_generator(P, Q);
+  }
+  if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
+  return method;
+}
+
+// The bitmaps of one collection in caller order, `method` one of Xor, Set,
+// Next.  The offsets are validated first (set sizes, side table and
+// counters come from `ar`), the token order on the way.  No host memory is
+// allocated.
+int build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint64_t *out, hipStream_t st,
+                  Arena &ar) {
+  const uint64_t n = s->n_sets;
+  if (n == 0) return SSJ_OK;
+  SideDesc side{};
+  side.offsets = s->offsets;
+  side.tokens = s->tokens;
+  side.n_tokens = s->n_tokens;
+  side.base = 0;
+  side.n = (uint32_t)n;
+  side.blk0 = 0;
+  SideDesc *d_side = ar.alloc<SideDesc>(1);
+  JoinCounters *ctr = ar.alloc<JoinCounters>(1);
+  uint32_t *sizes = ar.alloc<uint32_t>(n);
+  uint32_t *side_of = ar.alloc<uint32_t>(n);
+  h2d(d_side, &side, 1, st);
+  check(launch_reset_all(ctr, st));
+  check(launch_set_sizes(d_side, 1, n, sizes, side_of, ctr, st));
+  JoinCounters ctr_h{};
+  d2h(&ctr_h, ctr, 1, st);
+  sync(st);
+  if (ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
+  check(launch_build_bitmaps(d_side, 1, bitmap_seg_blocks(n), n, nullptr, nullptr, nullptr,
+                             b_bits, method, b_bits / 64, out, ctr, st));
+  d2h(&ctr_h, ctr, 1, st);
+  sync(st);
+  if (ctr_h.error & kErrUnsorted) return SSJ_E_UNSORTED;
+  return SSJ_OK;
+}
+
+// Device memory of ssj_build_bitmaps_noalloc: side table, counters and the
+// set sizes of one collection, in a fixed array of every device.  Host code
+// reaches a device's copy only through the address hipGetSymbolAddress
+// returns for it (kept per device in g_scratch).
+constexpr uint64_t kScratchBytes = 32ull << 20;
+constexpr int kScratchDevices = 64;
+constexpr uint64_t round256(uint64_t b) { return (b + 255) & ~255ull; }
+static_assert(round256(sizeof(SideDesc)) + round256(sizeof(JoinCounters)) +
+                      2 * round256(4ull * SSJ_NOALLOC_MAX_SETS) <= kScratchBytes,
+              "SSJ_NOALLOC_MAX_SETS sets fit the scratch array");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchSlot {
+  std::mutex mu;       // held for a whole call: calls on one device never overlap
+  void *ptr = nullptr; // the device's copy of `scratch`
+};
+ScratchSlot g_scratch[kScratchDevices];
+
 }  // namespace
 }  // namespace ssj
 
@@ -1518,37 +1599,50 @@ int ssj_build_bitmaps(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p
                       uint64_t *bitmaps_dev, void *hip_stream) {
   using namespace ssj;
   try {
-    validate_sets(s);
-    if (b_bits < 64 || b_bits > 4096 || b_bits % 64) return SSJ_E_INVALID;
-    if (method < SSJ_BM_XOR || method > SSJ_BM_COMBINED) return SSJ_E_UNSUPPORTED;
-    if (method == SSJ_BM_COMBINED) {
-      // Alg. 6 by the normalized value 2t/(1+t) of the Jaccard threshold
-      check_threshold(SSJ_SIM_JACCARD, p, q);
-      uint64_t P = 0, Q = 1;
-      normalized_threshold(SSJ_SIM_JACCARD, p, q, P, Q);
-      method = combined_generator(P, Q);
-    }
-    if (s->n_sets > 0 && !bitmaps_dev) return SSJ_E_INVALID;
+    const int m = bitmap_args(s, b_bits, method, p, q, bitmaps_dev);
+    if (m < 0) return m;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Arena ar(st);
-    Space A;
-    space_begin(A, &s, 1, ar, st);
-    sync(st);
-    if (A.ctr_h.error & (kErrOffsets | kErrTooBig)) return SSJ_E_INVALID;
-    if (A.n == 0) return SSJ_OK;
-    // caller order: no permutation
-    check(launch_build_bitmaps(A.d_sides, 1, A.seg_blocks, A.n, nullptr, nullptr, nullptr,
-                               b_bits, method, b_bits / 64, bitmaps_dev, A.ctr, st));
-    d2h(&A.ctr_h, A.ctr, 1, st);
-    sync(st);
-    if (A.ctr_h.error & kErrUnsorted) return SSJ_E_UNSORTED;
+    return build_bitmaps(s, b_bits, m, bitmaps_dev, st, ar);
   } catch (const Fail &f) {
     (void)hipGetLastError();
     return f.code;
   } catch (const std::bad_alloc &) {
     return SSJ_E_NOMEM;
   }
-  return SSJ_OK;
+}
+
+int ssj_build_bitmaps_noalloc(const ssj_sets *s, uint32_t b_bits, int method, uint32_t p,
+                              uint32_t q, uint64_t *bitmaps_dev, void *hip_stream) {
+  using namespace ssj;
+  const int m = bitmap_args(s, b_bits, method, p, q, bitmaps_dev);
+  if (m < 0) return m;
+  if (s->n_sets > SSJ_NOALLOC_MAX_SETS) return SSJ_E_UNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+    (void)hipGetLastError();
+    return SSJ_E_DEVICE;
+  }
+  ScratchSlot &slot = g_scratch[dev];
+  std::lock_guard<std::mutex> lk(slot.mu);  // one call at a time per device
+  if (!slot.ptr) {
+    // the device's copy of the array: its address is known only at run time
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return SSJ_E_DEVICE;
+    }
+    slot.ptr = ptr;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  try {
+    Arena ar(st, slot.ptr, kScratchBytes);
+    return build_bitmaps(s, b_bits, m, bitmaps_dev, st, ar);
+  } catch (const Fail &f) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    return f.code;
+  }
 }
 
 int ssj_self_join(const ssj_sets *s, const uint64_t *bitmaps_dev, uint32_t b_bits, int sim,
