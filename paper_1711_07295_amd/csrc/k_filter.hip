@@ -690,60 +690,78 @@ __device__ __forceinline__ bool emit_mfma(const MRows<W, RT> &rw, const uint4 (&
   return true;
 }
 
-// Fast path of one step: columns [j0, j0 + 32) against the wave's rows.
-// Leaves each row tile's largest bit pattern (as an integer) in mx and
-// returns whether one reaches its threshold (thr_bits).  Integer maxima:
-// float maxima would first quiet possible signalling NaNs, two more
-// instructions per row tile.
+// The dot products of the step's columns `a` with row tile rt.
 template <int W, int RT>
-__device__ __forceinline__ bool fast_mfma(const uint4 (&a)[W], const MRows<W, RT> &rw,
+__device__ __forceinline__ v16f_t products(const uint4 (&a)[W], const MRows<W, RT> &rw, int rt) {
+  v16f_t t = {};
+#pragma unroll
+  for (int kb = 0; kb < W; ++kb) t = mfma_pm1(a[kb], rw.sg[rt][kb], t);
+  return t;
+}
+
+// Largest of the 16 dot products of a lane (one row, 16 columns) as a bit
+// pattern compared as an integer: a tree of 3-input maxima.
+__device__ __forceinline__ int32_t max16(const v16f_t &x) {
+  int32_t b[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) b[v] = __float_as_int(x[v]);
+  int32_t m0 = max(max(b[0], b[1]), b[2]);
+  int32_t m1 = max(max(b[3], b[4]), b[5]);
+  int32_t m2 = max(max(b[6], b[7]), b[8]);
+  int32_t m3 = max(max(b[9], b[10]), b[11]);
+  int32_t m4 = max(max(b[12], b[13]), b[14]);
+  m0 = max(max(m0, m1), m2);
+  m3 = max(max(m3, m4), b[15]);
+  return max(m0, m3);
+}
+
+// Fast path of one step: columns [j0, j0 + 32) (operands `a`) against the
+// wave's rows.  Leaves each row tile's largest bit pattern (as an integer)
+// in mx and returns whether one reaches its threshold (thr_bits).  Integer
+// maxima: float maxima would first quiet possible signalling NaNs, two
+// more instructions per row tile.
+//
+// The products run one row tile ahead of their reduction, across steps:
+// product number k (row tile k mod RT of step k / RT) goes into
+// accumulator k mod 3 and is reduced while product k + 1 runs on the
+// matrix cores; the last row tile's reduction overlaps the first product
+// of the next step (operands `an`, the next step's columns, already
+// loaded).  K is the step's place in the three-step unrolled loop, so that
+// every accumulator index is a constant; on entry accumulator (K RT) mod 3
+// holds this step's first product.  When the sweep ends after this step,
+// that last product is simply dropped.
+template <int W, int RT, int K>
+__device__ __forceinline__ bool fast_mfma(const uint4 (&a)[W], const uint4 (&an)[W],
+                                          const MRows<W, RT> &rw, v16f_t (&acc)[3],
                                           int32_t (&mx)[RT]) {
-  // Two accumulators: row tile rt's products go into the registers of row
-  // tile rt-2 once those are reduced, so one row tile's MFMA runs while the
-  // previous one is reduced and fewer registers hold dot products (the
-  // waves per SIMD are bounded by registers).
   unsigned long long hit = 0;
-  v16f_t acc[2];
 #pragma unroll
-  for (int rt = 0; rt < RT + 2; ++rt) {
-    if (rt >= 2) {
-      const v16f_t &x = acc[rt & 1];
-      int32_t b[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) b[v] = __float_as_int(x[v]);
-      // max of the 16 patterns, as a tree of 3-input maxima
-      int32_t m0 = max(max(b[0], b[1]), b[2]);
-      int32_t m1 = max(max(b[3], b[4]), b[5]);
-      int32_t m2 = max(max(b[6], b[7]), b[8]);
-      int32_t m3 = max(max(b[9], b[10]), b[11]);
-      int32_t m4 = max(max(b[12], b[13]), b[14]);
-      m0 = max(max(m0, m1), m2);
-      m3 = max(max(m3, m4), b[15]);
-      mx[rt - 2] = max(m0, m3);
-      hit |= __ballot(mx[rt - 2] >= rw.thr_bits[rt - 2]);
-    }
-    if (rt < RT) {
-      v16f_t t = {};
-#pragma unroll
-      for (int kb = 0; kb < W; ++kb) t = mfma_pm1(a[kb], rw.sg[rt][kb], t);
-      acc[rt & 1] = t;
-    }
+  for (int rt = 0; rt < RT; ++rt) {
+    constexpr int base = K * RT;
+    const int cur = (base + rt) % 3, nxt = (base + rt + 1) % 3;
+    acc[nxt] = rt + 1 < RT ? products<W, RT>(a, rw, rt + 1) : products<W, RT>(an, rw, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mx[rt] = max16(acc[cur]);
+    hit |= __ballot(mx[rt] >= rw.thr_bits[rt]);
     __builtin_amdgcn_sched_barrier(0);
   }
+  // the next step's first product stays ahead of the branch that ends the
+  // step (the compiler would otherwise sink it below, into the next step)
+  asm volatile("" ::"v"(acc[(K * RT + RT) % 3]));
   return hit != 0;
 }
 
 // The steps of columns [j, g1) of one size group.  Column loads run two
 // steps ahead in a ring of three register buffers; the loop is unrolled by
 // three so that the ring turns without register copies (a copy of a buffer
-// still being loaded would wait for that load).  A step that keeps
-// something leaves the loop for the one slow path, laid out once
-// (instruction cache: the kernel stays small); the slow path turns the
-// ring by register moves so that the loop goes on at the next step with
-// the buffers already loaded.  Every branch leaves the loop, none enters
-// it in the middle, and every buffer is read on both sides of each exit:
-// the compiler keeps the ring in fixed registers and leaves the loads
-// where they are.
+// still being loaded would wait for that load) and the accumulators of the
+// fast path keep constant indices.  A step that keeps something leaves the
+// loop for the one slow path, laid out once (instruction cache: the kernel
+// stays small); the slow path turns the ring by register moves so that the
+// loop goes on at the next step with the buffers already loaded.  Every
+// branch leaves the loop, none enters it in the middle, and every buffer
+// is read on both sides of each exit: the compiler keeps the ring in fixed
+// registers and leaves the loads where they are.
 template <int W, int RT>
 __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, uint32_t n_cols,
                                            const MRows<W, RT> &rw, uint32_t j, uint32_t g1,
@@ -752,28 +770,30 @@ __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, ui
   const uint32_t loff = (lane & 31u) * 32u + (lane >> 5) * 16u;
   uint4 b0[W], b1[W], b2[W];
   int32_t mx[RT];
+  v16f_t acc[3];
   uint32_t j0 = j;
   load_cols<W>(sg_cols, n_cols, j0, loff, b0);
   load_cols<W>(sg_cols, n_cols, j0 + 32, loff, b1);
   for (;;) {
     int phase;  // the ring buffer that holds the columns of step j0
+    acc[0] = products<W, RT>(b0, rw, 0);
     for (;;) {
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b2);
-      if (__builtin_expect(fast_mfma<W, RT>(b0, rw, mx), 0)) {
+      if (__builtin_expect(fast_mfma<W, RT, 0>(b0, b1, rw, acc, mx), 0)) {
         phase = 0;
         break;
       }
       skip = 0;
       if ((j0 += 32) >= g1) return true;
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b0);
-      if (__builtin_expect(fast_mfma<W, RT>(b1, rw, mx), 0)) {
+      if (__builtin_expect(fast_mfma<W, RT, 1>(b1, b2, rw, acc, mx), 0)) {
         phase = 1;
         break;
       }
       skip = 0;
       if ((j0 += 32) >= g1) return true;
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b1);
-      if (__builtin_expect(fast_mfma<W, RT>(b2, rw, mx), 0)) {
+      if (__builtin_expect(fast_mfma<W, RT, 2>(b2, b0, rw, acc, mx), 0)) {
         phase = 2;
         break;
       }

@@ -18,8 +18,9 @@
 // large for that width (its bits saturate) are tested again at the wide
 // width, 4096 bits, when both sets have wide bitmaps.
 //
-// Grid-stride over the queue, one survivor per lane; results are appended
-// with one atomic per wave (ballot + lane rank).
+// Each wave packs the real entries of its run of the queue (the filter's
+// chunks end in sentinels) so that every lane verifies a survivor; results
+// are appended with one atomic per wave and round (ballot + lane rank).
 #include "ssj_internal.h"
 
 namespace ssj {
@@ -74,85 +75,104 @@ __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restr
   return o >= need;
 }
 
+// Hamming distance of two bitmaps of w 64-bit words, two words per
+// 16-byte load (both bitmaps start on a 16-byte boundary when w is even).
+__device__ __forceinline__ uint32_t distance(const uint64_t *__restrict__ x,
+                                             const uint64_t *__restrict__ y, uint32_t w) {
+  uint32_t h = 0;
+  if ((w & 1u) == 0) {
+    const uint4 *a = reinterpret_cast<const uint4 *>(x), *b = reinterpret_cast<const uint4 *>(y);
+    for (uint32_t k = 0; k < w / 2; ++k) {
+      const uint4 p = a[k], q = b[k];
+      h += (uint32_t)__popc(p.x ^ q.x) + (uint32_t)__popc(p.y ^ q.y) +
+           (uint32_t)__popc(p.z ^ q.z) + (uint32_t)__popc(p.w ^ q.w);
+    }
+  } else {
+    for (uint32_t k = 0; k < w; ++k) h += (uint32_t)__popcll(x[k] ^ y[k]);
+  }
+  return h;
+}
+
+// Verify one survivor (row x, column y of the two spaces): its result key,
+// or false.  Sizes, the task's least overlap and the cascade bitmaps come
+// from arrays indexed by the queue entry itself, so the false survivors
+// that the wider bitmaps reject (most of them) never touch the caller's
+// offsets or tokens.
+__device__ __forceinline__ bool verify_entry(uint32_t x, uint32_t y, const VerifySpace &rows,
+                                             const VerifySpace &cols,
+                                             const uint32_t *__restrict__ side_task,
+                                             const TaskDesc *__restrict__ tasks,
+                                             const uint32_t *__restrict__ tables, int ib, int jb,
+                                             uint32_t survivors_only, uint32_t w2,
+                                             unsigned long long &key) {
+  const uint32_t sr = rows.side_of[x], sc = cols.side_of[y];
+  const uint32_t a = rows.sizes[x], c = cols.sizes[y];
+  const uint32_t task = side_task[sr];
+  const TaskDesc &td = tasks[task];
+  bool hit = true;
+  if (!survivors_only) {
+    const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
+                                                   : tables[td.omin_off + a + c];
+    const int64_t slack = (int64_t)a + c - 2 * (int64_t)need;
+    // second bitmap test at the cascade width (Theorem 1 holds at every
+    // width): most false survivors of a narrow class end here
+    hit = a != 0 && c != 0 && slack >= 0;
+    if (hit && rows.bm2)
+      hit = (int64_t)distance(rows.bm2 + (size_t)x * w2, cols.bm2 + (size_t)y * w2, w2) <= slack;
+    // and at the wide width when both sets have wide bitmaps (sets too
+    // large for the cascade width, whose bits saturate)
+    if (hit && rows.bmw) {
+      const uint32_t lr = rows.wide_lo[sr], lc = cols.wide_lo[sc];
+      if (x >= lr && y >= lc)
+        hit = (int64_t)distance(rows.bmw + (size_t)(rows.wide_slot[sr] + (x - lr)) * kWideWords,
+                                cols.bmw + (size_t)(cols.wide_slot[sc] + (y - lc)) * kWideWords,
+                                kWideWords) <= slack;
+    }
+    if (hit) {
+      const SideDesc &dr = rows.sides[sr], &dc = cols.sides[sc];
+      const uint64_t r0 = dr.offsets[rows.perm[x]], s0 = dc.offsets[cols.perm[y]];
+      hit = overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
+    }
+  }
+  if (hit) {
+    uint32_t ki = rows.perm[x], kj = cols.perm[y];
+    if (td.self && kj < ki) {
+      const uint32_t t = ki;
+      ki = kj;
+      kj = t;
+    }
+    key = ((unsigned long long)ki << jb) | kj;
+    if (ib + jb < 64) key |= (unsigned long long)task << (ib + jb);
+  }
+  return hit;
+}
+
+// Each wave verifies a contiguous run of the queue.  The queue holds the
+// filter waves' chunks, whose unused ends are sentinels; the wave reads its
+// run 64 entries at a time and packs the real ones into an LDS list, and
+// verifies them 64 at a time, so that every lane of a verification round
+// has a survivor (the round's length is that of its longest merge).
 __global__ __launch_bounds__(kBlock) void k_verify(
     const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
     const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
     const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only, uint32_t w2,
     unsigned long long *__restrict__ results, unsigned long long results_cap,
     JoinCounters *__restrict__ ctr) {
+  __shared__ uint2 pend[kBlock / 64][128];
+  uint2 *buf = pend[threadIdx.x >> 6];
   const uint32_t lane = threadIdx.x & 63;
   unsigned long long count = ctr->queue_count;
   if (count > cap) count = cap;
-  const unsigned long long stride = (unsigned long long)gridDim.x * kBlock;
-  const unsigned long long start = (unsigned long long)blockIdx.x * kBlock + threadIdx.x;
-  // every lane of a wave runs the same number of iterations
-  const unsigned long long wave0 = start - lane;
-  const int tshift = ib + jb;
-  uint32_t surv = 0;
-  for (unsigned long long e0 = wave0; e0 < count; e0 += stride) {
-    const unsigned long long e = e0 + lane;
-    bool hit = false;
+  const unsigned long long windows = (count + 63) / 64;
+  const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
+  const unsigned long long wave = (unsigned long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const unsigned long long per = (windows + n_waves - 1) / n_waves;
+  const unsigned long long w0 = min(wave * per, windows), w1 = min(w0 + per, windows);
+  uint32_t fill = 0, surv = 0;
+  auto round = [&](uint2 qe, bool ok) {
     unsigned long long key = 0;
-    if (e < count) {
-      const uint2 qe = queue[e];
-      if (qe.x < rows.n && qe.y < cols.n) {
-        ++surv;
-        const uint32_t sr = rows.side_of[qe.x], sc = cols.side_of[qe.y];
-        const SideDesc dr = rows.sides[sr];
-        const SideDesc dc = cols.sides[sc];
-        const uint32_t task = side_task[sr];
-        const uint32_t x = rows.perm[qe.x], y = cols.perm[qe.y];
-        const uint64_t r0 = dr.offsets[x], r1 = dr.offsets[x + 1];
-        const uint64_t s0 = dc.offsets[y], s1 = dc.offsets[y + 1];
-        const uint32_t a = (uint32_t)(r1 - r0), c = (uint32_t)(s1 - s0);
-        if (survivors_only) {
-          hit = true;
-        } else {
-          const TaskDesc &td = tasks[task];
-          const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
-                                                         : tables[td.omin_off + a + c];
-          // second bitmap test at the cascade width (Theorem 1 holds at
-          // every width): most false survivors of a narrow class end here
-          bool pass = true;
-          if (rows.bm2) {
-            const uint64_t *bx = rows.bm2 + (size_t)qe.x * w2;
-            const uint64_t *by = cols.bm2 + (size_t)qe.y * w2;
-            uint32_t h = 0;
-            for (uint32_t w = 0; w < w2; ++w) h += (uint32_t)__popcll(bx[w] ^ by[w]);
-            pass = (int64_t)h <= (int64_t)a + c - 2 * (int64_t)need;
-          }
-          // and at the wide width when both sets have wide bitmaps (sets too
-          // large for the cascade width, whose bits saturate)
-          if (pass && rows.bmw) {
-            const uint32_t lr = rows.wide_lo[sr], lc = cols.wide_lo[sc];
-            if (qe.x >= lr && qe.y >= lc) {
-              const uint4 *bx = reinterpret_cast<const uint4 *>(
-                  rows.bmw + (size_t)(rows.wide_slot[sr] + (qe.x - lr)) * kWideWords);
-              const uint4 *by = reinterpret_cast<const uint4 *>(
-                  cols.bmw + (size_t)(cols.wide_slot[sc] + (qe.y - lc)) * kWideWords);
-              uint32_t h = 0;
-              for (uint32_t w = 0; w < kWideWords / 2; ++w) {
-                const uint4 p = bx[w], q = by[w];
-                h += (uint32_t)__popc(p.x ^ q.x) + (uint32_t)__popc(p.y ^ q.y) +
-                     (uint32_t)__popc(p.z ^ q.z) + (uint32_t)__popc(p.w ^ q.w);
-              }
-              pass = (int64_t)h <= (int64_t)a + c - 2 * (int64_t)need;
-            }
-          }
-          hit = a != 0 && c != 0 && pass &&
-                overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
-        }
-        if (hit) {
-          uint32_t ki = x, kj = y;
-          if (tasks[task].self && y < x) {
-            ki = y;
-            kj = x;
-          }
-          key = ((unsigned long long)ki << jb) | kj;
-          if (tshift < 64) key |= (unsigned long long)task << tshift;
-        }
-      }
-    }
+    const bool hit = ok && verify_entry(qe.x, qe.y, rows, cols, side_task, tasks, tables, ib, jb,
+                                        survivors_only, w2, key);
     const unsigned long long m = __ballot(hit);
     if (m) {
       unsigned long long base = 0;
@@ -163,6 +183,31 @@ __global__ __launch_bounds__(kBlock) void k_verify(
         if (pos < results_cap) results[pos] = key;
       }
     }
+  };
+  for (unsigned long long w = w0; w < w1; ++w) {
+    const unsigned long long e = w * 64 + lane;
+    uint2 qe = make_uint2(kSentinel, kSentinel);
+    if (e < count) qe = queue[e];
+    const bool valid = qe.x < rows.n && qe.y < cols.n;
+    const unsigned long long m = __ballot(valid);
+    if (valid) buf[fill + (uint32_t)__popcll(m & __lanemask_lt())] = qe;
+    fill += (uint32_t)__popcll(m);  // < 128: at most 63 were left over
+    if (fill >= 64) {
+      __builtin_amdgcn_wave_barrier();
+      const uint2 mine = buf[lane], carry = buf[64 + lane];
+      __builtin_amdgcn_wave_barrier();
+      fill -= 64;
+      if (lane < fill) buf[lane] = carry;
+      __builtin_amdgcn_wave_barrier();
+      ++surv;
+      round(mine, true);
+    }
+  }
+  if (fill) {
+    __builtin_amdgcn_wave_barrier();
+    const uint2 mine = buf[lane];
+    surv += lane < fill ? 1u : 0u;
+    round(mine, lane < fill);
   }
   // survivors seen, one atomic per wave
   uint32_t s = surv;

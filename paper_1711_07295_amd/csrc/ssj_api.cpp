@@ -1124,9 +1124,9 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     if (!jc.cols_resident) space_wide(C, ar, st);
   }
   const bool wide = cascade && R.bmw && C.bmw;
-  const VerifySpace vrows{R.d_sides, R.side_of, R.perm, cascade ? R.bitmaps(w2) : nullptr,
+  const VerifySpace vrows{R.d_sides, R.side_of, R.perm, R.sizes, cascade ? R.bitmaps(w2) : nullptr,
                           (uint32_t)R.n, wide ? R.bmw : nullptr, R.wide_lo, R.wide_slot};
-  const VerifySpace vcols{C.d_sides, C.side_of, C.perm, cascade ? C.bitmaps(w2) : nullptr,
+  const VerifySpace vcols{C.d_sides, C.side_of, C.perm, C.sizes, cascade ? C.bitmaps(w2) : nullptr,
                           (uint32_t)C.n, wide ? C.bmw : nullptr, C.wide_lo, C.wide_slot};
   if (!cascade) w2 = 0;
 

@@ -302,7 +302,9 @@ struct VerifySpace {
   const SideDesc *sides;
   const uint32_t *side_of;
   const uint32_t *perm;
-  const uint64_t *bm2;     // size-order bitmaps at the cascade width, or NULL
+  const uint32_t *sizes;   // set sizes in size order
+  const uint64_t *bm2;     // size-order bitmaps at the cascade width (an even
+                           // number of words per set), or NULL
   uint32_t n;              // sets in the space
   const uint64_t *bmw;     // wide bitmaps (kWideWords words per slot), or NULL
   const uint32_t *wide_lo; // per side: first position with a wide bitmap (~0u: none)
