@@ -34,6 +34,11 @@ PEAK_FP4 = 10.1e15                # dense fp4 MFMA flop/s (published)
 PEAK_HBM = 8.0e12                 # bytes/s
 MFMA_BITS = (64, 128, 256)        # widths the matrix-core filter runs
 MFMA_MIN_BAND = 1 << 26           # ... and b = 256 only for a class of at least this many band pairs
+# arithmetic of the path: the matrix-core filter multiplies +-1 values held in
+# fp4 and accumulates them in fp32 (exact integers); every other step is
+# integer arithmetic on uint32 tokens, sizes and counts
+DTYPE_MFMA = "fp4 (+-1) products, fp32 accumulation (exact); u32 elsewhere"
+DTYPE_INT = "u32"
 
 # HBM bytes per launch of the dominant filter launch (the b = 64 class of the
 # 1,000,000-set workload at 4/5, matrix-core kernel), from two rocprofv3
@@ -73,7 +78,7 @@ def cpu_baseline(col, p, q, sim=0, fraction=0.005):
     every 1/fraction-th row of the size order, each against its whole band."""
     import numpy as np
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_threads()
     order = oracle.size_order(col.offsets)
     step = int(round(1 / fraction))
     rows = np.arange(step // 2, col.n_sets, step, dtype=np.uint64)
@@ -82,8 +87,26 @@ def cpu_baseline(col, p, q, sim=0, fraction=0.005):
                                            order=order, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": evaluated / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
             "sample": f"{len(rows)} rows (every {step}th in size order) x their length band: "
-                      f"{evaluated} pairs merged in {dt:.1f} s"}
+                      f"{evaluated} pairs merged in {dt:.1f} s on {threads} threads"}
+
+
+def host_threads():
+    """Threads the oracle runs on: every CPU this process may use, at most 16
+    (the host share that goes with one GPU)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -95,6 +118,11 @@ def main():
                     help="serve mode: measured batches per load (plus 100 warm-up)")
     ap.add_argument("--resident", type=int, default=5_000_000,
                     help="serve mode: sets in the resident index")
+    ap.add_argument("--slots", type=int, default=2,
+                    help="served form: calls in flight at once (continuous batching)")
+    ap.add_argument("--serve-batches-default", type=int, default=300,
+                    help="default mode: measured query batches of the served leg "
+                         "(0 = no served leg)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="selfjoin-1m")
@@ -192,10 +220,11 @@ def main():
                                                  s0["class_bits"][:ncls],
                                                  s0["class_ops"][:ncls]))]
     line = {
-        "metric": "pairs/sec (bitmap-filtered join, 1M sets, J>=0.8)",
+        "metric": "pairs/sec (bitmap-filtered join, 1M sets, J>=0.8) + p50/p99 query latency",
         "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE_MFMA if roof["bound"] == "mfma" else DTYPE_INT, "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
                    "threshold": f"{args.p}/{args.q}", "similarity": args.sim,
                    "cutoff": args.cutoff, "filter": "valu" if args.valu else "mfma",
@@ -214,6 +243,23 @@ def main():
         log("cpu baseline: oracle on a 0.5% row sample ...")
         line["cpu_baseline"] = cpu_baseline(col, args.p, args.q, sim)
         log(f"cpu baseline: {line['cpu_baseline']}")
+    if args.serve_batches_default:
+        # the metric's latency half: query batches against the resident
+        # 5,000,000-set index at 0.95 of the plain service rate
+        del dev
+        torch.cuda.empty_cache()
+        sv = served_legs(args.resident, args.serve_batches_default, (0.95,), slots=args.slots)
+        head = sv["loads"][0]
+        line["latency"] = {"p50_ms": head["continuous"]["p50_ms"],
+                           "p99_ms": head["continuous"]["p99_ms"], "rho": 0.95,
+                           "workload": f"served-{sv['resident_sets']}",
+                           "measured_batches": sv["batches"] - sv["warm_up_batches"],
+                           "plain_p50_ms": head["plain"]["p50_ms"],
+                           "plain_p99_ms": head["plain"]["p99_ms"],
+                           "plain_service_rate": sv["plain_service_rate"]}
+        line["served_vs_plain"] = {"p50": head["p50_plain_over_continuous"],
+                                   "p99": head["p99_plain_over_continuous"]}
+        line["served"] = sv
     print(json.dumps(line), flush=True)
 
 
@@ -316,7 +362,7 @@ def run_batch(args):
         "metric": "pairs/sec (batched bitmap-filtered self-joins)",
         "value": band / (ms / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_MFMA, "data": "synthetic",
         "config": {"workload": f"batched-{len(inst)}", "instances": len(inst),
                    "n_sets": n_sets, "n_tokens": n_tok,
                    "b_bits": args.bits if args.bits else "auto", "band_pairs": band,
@@ -335,7 +381,14 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def run_serve(args):
+def served_legs(resident, n_measured, rhos, warm=100, cutoff=False, bits=0, slots=2):
+    """The served form on a resident index of ``resident`` sets: the plain
+    service rate mu (one batch per call, back to back), then for each load
+    rho Poisson arrivals at rho * mu served twice -- by the plain server (one
+    call per batch, first come first served) and by continuous batching
+    (``slots`` calls in flight, each admitting every waiting batch that fits
+    the memory budget).  Latency is arrival to pairs in host memory; the
+    first ``warm`` batches of every run are not measured."""
     import numpy as np
     import torch
 
@@ -343,60 +396,78 @@ def run_serve(args):
     import paper_1711_07295_amd as ssj
     from paper_1711_07295_amd.serve import ContinuousBatcher, poisson_arrivals
 
-    warm = 100
     t0 = time.perf_counter()
-    sw = gen.served_workload(warm + args.serve_batches, resident_sets=args.resident)
+    sw = gen.served_workload(warm + n_measured, resident_sets=resident)
     log(f"generated resident {sw.resident.n_sets} sets and {len(sw.batches)} query batches "
         f"({sum(b.n_sets for b in sw.batches)} sets) in {time.perf_counter() - t0:.1f} s")
     t1 = time.perf_counter()
-    idx = ssj.Index(ssj.to_device(sw.resident.offsets, sw.resident.tokens), b_bits=args.bits)
+    idx = ssj.Index(ssj.to_device(sw.resident.offsets, sw.resident.tokens), b_bits=bits)
     torch.cuda.synchronize()
     log(f"index built in {time.perf_counter() - t1:.2f} s")
-    srv = ContinuousBatcher(idx, flags=ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0)
+    flags = ssj.SSJ_FLAG_CUTOFF if cutoff else 0
+    plain = ContinuousBatcher(idx, slots=1, max_batches_per_call=1, flags=flags)
+    cont = ContinuousBatcher(idx, slots=slots, flags=flags)
     batches, thr = sw.batches, sw.thresholds
+    n = len(batches)
+    plain.run(batches[:warm], thr[:warm], np.zeros(warm))
+    cont.run(batches[:warm], thr[:warm], np.zeros(warm))
     # plain service rate: one batch per call, back to back
-    n_plain = min(300, len(batches))
-    srv.run(batches[:warm], thr[:warm], np.zeros(warm))
-    t1 = time.perf_counter()
-    for k in range(n_plain):
-        srv.run([batches[k]], [thr[k]], [0.0])
-    mu = n_plain / (time.perf_counter() - t1)
+    r = plain.run(batches[warm:], thr[warm:], np.zeros(n - warm))
+    mu = (n - warm) / r.wall_s
     log(f"plain service rate: {mu:.1f} batches/s")
-    loads = []
-    for rho in (0.5, 0.8, 0.95, 1.2):
-        arr = poisson_arrivals(len(batches), rho * mu, seed=int(rho * 1000))
-        r = srv.run(batches, thr, arr)
+
+    def summary(r, rho):
         m = slice(warm, None)  # measured batches
         lat, wait = r.latency_s[m] * 1e3, r.wait_s[m] * 1e3
-        span = float(arr[-1] - arr[warm]) if len(arr) > warm + 1 else r.wall_s
-        ent = {"rho": rho, "arrival_rate": rho * mu, "p50_ms": float(np.percentile(lat, 50)),
+        ent = {"rho": rho, "p50_ms": float(np.percentile(lat, 50)),
                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                "wait_p50_ms": float(np.percentile(wait, 50)),
                "wait_p99_ms": float(np.percentile(wait, 99)),
-               "batches_per_s": len(batches) / r.wall_s, "pairs_per_s": r.band_pairs / r.wall_s,
+               "batches_per_s": n / r.wall_s, "pairs_per_s": r.band_pairs / r.wall_s,
                "calls": r.calls, "mean_batches_per_call": float(r.batches_per_call.mean()),
-               "results": r.results, "measured_span_s": span}
+               "max_in_flight": r.max_in_flight, "peak_admitted_bytes": r.peak_bytes,
+               "results": r.results}
         det = r.calls_detail
         ent["call_ms"] = {k: float(np.mean([d[k] for d in det]))
                           for k in ("wall_ms", "upload_ms", "ms_total", "ms_prepare", "ms_filter",
                                     "ms_verify", "ms_emit")}
-        ent["mean_sets_per_call"] = float(np.mean([d["sets"] for d in det]))
+        return ent
+
+    loads = []
+    for rho in rhos:
+        arr = poisson_arrivals(n, rho * mu, seed=int(rho * 1000))
+        ent = {"rho": rho, "arrival_rate": rho * mu,
+               "plain": summary(plain.run(batches, thr, arr), rho),
+               "continuous": summary(cont.run(batches, thr, arr), rho)}
+        ent["p99_plain_over_continuous"] = ent["plain"]["p99_ms"] / ent["continuous"]["p99_ms"]
+        ent["p50_plain_over_continuous"] = ent["plain"]["p50_ms"] / ent["continuous"]["p50_ms"]
         loads.append(ent)
-        log(f"rho {rho}: {ent}")
+        log(f"rho {rho}: plain p50/p99 {ent['plain']['p50_ms']:.2f}/{ent['plain']['p99_ms']:.2f} ms, "
+            f"continuous {ent['continuous']['p50_ms']:.2f}/{ent['continuous']['p99_ms']:.2f} ms, "
+            f"{ent['continuous']['calls']} calls, up to {ent['continuous']['max_in_flight']} in flight")
     idx.close()
-    head = [e for e in loads if e["rho"] == 0.95][0]
+    return {"resident_sets": sw.resident.n_sets, "batches": n, "warm_up_batches": warm,
+            "slots": slots, "plain_service_rate": mu, "b_bits": bits if bits else "auto",
+            "cutoff": cutoff, "loads": loads}
+
+
+def run_serve(args):
+    sv = served_legs(args.resident, args.serve_batches, (0.5, 0.8, 0.95, 1.2), cutoff=args.cutoff,
+                     bits=args.bits, slots=args.slots)
+    head = [e for e in sv["loads"] if e["rho"] == 0.95][0]
+    c = head["continuous"]
     line = {
         "metric": "pairs/sec + p50/p99 query latency (served R-S joins, continuous batching)",
-        "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
-        "steps": args.serve_batches, "warmup": warm, "ms_per_step": head["mean_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "value": c["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.serve_batches, "warmup": sv["warm_up_batches"], "ms_per_step": c["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_MFMA,
         "data": "synthetic",
-        "config": {"workload": f"served-{sw.resident.n_sets}", "resident_sets": sw.resident.n_sets,
-                   "batches": len(batches),
-                   "b_bits": args.bits if args.bits else "auto", "cutoff": args.cutoff,
-                   "plain_service_rate": mu},
-        "latency": {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "rho": 0.95},
-        "loads": loads,
+        "config": {"workload": f"served-{sv['resident_sets']}",
+                   **{k: v for k, v in sv.items() if k != "loads"}},
+        "latency": {"p50_ms": c["p50_ms"], "p99_ms": c["p99_ms"], "rho": 0.95,
+                    "plain_p50_ms": head["plain"]["p50_ms"],
+                    "plain_p99_ms": head["plain"]["p99_ms"]},
+        "loads": sv["loads"],
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)

@@ -179,3 +179,26 @@ def test_index_small_batches():
         got_cut, _ = idx.query(devs, ps, qs, flags=ssj.SSJ_FLAG_CUTOFF)
         for a, b in zip(got, got_cut):
             assert np.array_equal(a, b)
+
+
+def test_served_calls_overlap_and_give_the_same_pairs_alone_and_mixed():
+    """Continuous batching with two calls in flight on two streams: batches
+    that arrive while a call runs go into the other slot, and every batch's
+    pairs equal the oracle's R-S join (Eq. 1) and its own call alone."""
+    from paper_1711_07295_amd.serve import ContinuousBatcher
+    sw = gen.served_workload(16, resident_sets=20000, max_batch=500, seed=gen.SEED_BASE + 42)
+    res = sw.resident
+    with ssj.Index(_dev(res)) as idx:
+        arr = np.linspace(0.0, 0.004, len(sw.batches))
+        srv = ContinuousBatcher(idx, slots=2, memory_budget=8 << 30, queue_capacity=1 << 16,
+                                keep_pairs=True, max_batches_per_call=3)
+        r = srv.run(sw.batches, sw.thresholds, arr)
+        assert r.calls >= 6 and r.max_in_flight == 2, (r.calls, r.max_in_flight)
+        assert sorted({d["slot"] for d in r.calls_detail}) == [0, 1]
+        alone = ContinuousBatcher(idx, slots=1, keep_pairs=True, max_batches_per_call=1)
+        solo = alone.run(sw.batches, sw.thresholds, np.zeros(len(sw.batches)))
+        for x, (p, q), g, a in zip(sw.batches, sw.thresholds, r.pairs, solo.pairs):
+            want = oracle.rs_join(x.offsets, x.tokens, res.offsets, res.tokens, p, q)
+            assert np.array_equal(g, want), (x.n_sets, p, q)
+            assert np.array_equal(a, want)
+        assert r.results == solo.results == sum(len(g) for g in r.pairs)
