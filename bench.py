@@ -198,6 +198,9 @@ def main():
             f"emit {st['ms_emit']:.2f}  survivors {st['survivors']}  results {st['results']}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    graph = None
+    if args.bits == 0 and not args.valu and args.sim == "jaccard":
+        graph = graph_replay([dev], [args.p], [args.q], args, [pairs])
 
     band = stats[0]["band_pairs"]
     ms_per_step = total / args.steps * 1e3
@@ -239,6 +242,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if graph:
+        line["graph_replay"] = {**graph, "speedup_vs_call": ms_per_step / graph["ms_per_step"]}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 0.5% row sample ...")
         line["cpu_baseline"] = cpu_baseline(col, args.p, args.q, sim)
@@ -297,6 +302,34 @@ def roofline_of(stats_list, steps, valu=False):
             "ops_per_launch": s0["class_ops"][dom] / launches,
             "band_pairs_per_launch": band / launches, "avg_launch_ms": dom_ms / launches,
             "filter_stage": stage}
+
+
+def graph_replay(devs, ps, qs, args, want):
+    """ssj_plan_self_join_batch once, then ssj_plan_execute per step (the
+    first round replayed from a HIP graph); the pairs must equal ``want``
+    (the unprepared call's)."""
+    import numpy as np
+    import torch
+
+    import paper_1711_07295_amd as ssj
+
+    t0 = time.perf_counter()
+    plan = ssj.Plan(devs, ps, qs, b_bits=args.bits, tile_cols=args.tile_cols,
+                    flags=ssj.SSJ_FLAG_CUTOFF if args.cutoff else 0)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    got, _ = plan.execute()
+    same = len(got) == len(want) and all(np.array_equal(a, b) for a, b in zip(got, want))
+    torch.cuda.synchronize()
+    times = []
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        got, st = plan.execute()
+        times.append(time.perf_counter() - t1)
+    plan.close()
+    log(f"graph replay: {statistics.mean(times) * 1e3:.2f} ms per execution "
+        f"(plan {plan_ms:.1f} ms), same pairs: {same}")
+    return {"ms_per_step": statistics.mean(times) * 1e3, "plan_ms": plan_ms,
+            "same_pairs": bool(same), "steps": args.steps}
 
 
 def run_batch(args):
@@ -358,6 +391,8 @@ def run_batch(args):
     assert band == band_seq and stats[0]["results"] == res_seq
     ms = statistics.mean(times) * 1e3
     seq_ms = statistics.mean(seq_times) * 1e3
+    # the same instances prepared once, the first round replayed from a graph
+    graph = graph_replay(devs, ps, qs, args, got)
     line = {
         "metric": "pairs/sec (batched bitmap-filtered self-joins)",
         "value": band / (ms / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -371,6 +406,8 @@ def run_batch(args):
         "sequential": {"ms_per_step": seq_ms, "value": band / (seq_ms / 1e3),
                        "calls": len(inst)},
         "speedup_vs_sequential": seq_ms / ms,
+        "graph_replay": {**graph, "speedup_vs_call": ms / graph["ms_per_step"],
+                         "speedup_vs_sequential": seq_ms / graph["ms_per_step"]},
         "step_ms": {"p50": statistics.median(times) * 1e3,
                     "p99": float(np.percentile(np.array(times), 99)) * 1e3},
         "stage_ms": {k: statistics.mean(s[k] for s in stats)

@@ -1,6 +1,6 @@
 /*
  * ssj.h -- exact set similarity join with the Bitmap Filter on one AMD
- * Instinct MI355X (gfx950).  C ABI, version 2.
+ * Instinct MI355X (gfx950).  C ABI, version 3.
  *
  * Method: Sandes, Teodoro, Melo, "Bitmap Filter: Speeding up Exact Set
  * Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SSJ_ABI_VERSION 2
+#define SSJ_ABI_VERSION 3
 
 typedef enum {
   SSJ_OK = 0,
@@ -133,8 +133,11 @@ typedef struct {
 
 /* Optional knobs; pass NULL for the defaults. */
 typedef struct {
-  uint64_t queue_capacity; /* survivor-queue entries per drain; 0 = default;
-                              raised to at least 4096 */
+  uint64_t queue_capacity; /* survivor-queue entries per drain (8 bytes
+                              each, and as many 8-byte result keys), raised
+                              to at least 4096; 0 = the library's: 2^23 at
+                              first, quadrupled after each drain round that
+                              filled it, up to 2^29 */
   uint32_t tile_cols;      /* columns per filter tile; 0 = default */
   uint32_t flags;          /* SSJ_FLAG_* */
 } ssj_options;
@@ -322,6 +325,54 @@ int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
  * still be running. */
 void ssj_index_destroy(ssj_index *idx);
 
+/* A prepared self-join of one or more instances (the batched form): planned
+ * once, its first filter/verify round captured in a HIP graph, executed
+ * many times. */
+typedef struct ssj_plan ssj_plan;
+
+/*
+ * ssj_plan_self_join_batch -- plan the self-join of n_instances collections
+ * (each at its own threshold p[k] / q[k]; Eq. 1 per instance) once: size
+ * sort, length band (Table 2), width classes, tile plan and every buffer,
+ * in memory the plan owns.  The device work that reads the tokens --
+ * validation, the bitmaps of every width (Bitmap-Xor, Alg. 4), sign planes,
+ * the filter launch of every width class (Theorem 1, Eq. 2) and the
+ * verification of the survivors -- is captured in one HIP graph, which
+ * every ssj_plan_execute replays with one launch.  A plan depends on the
+ * set sizes only: the tokens may change between executions, the offsets
+ * and the buffers may not, and both must stay valid while the plan lives.
+ * Arguments as ssj_self_join_batch (n_instances >= 1); the caller's
+ * bitmaps are not taken (the plan builds its own).  Returns after
+ * hip_stream is synchronised.
+ *   out          receives the plan; NULL on error
+ * Errors as ssj_self_join_batch; SSJ_E_INVALID also for n_instances == 0.
+ */
+int ssj_plan_self_join_batch(const ssj_sets *sets, uint32_t n_instances, const uint32_t *p,
+                             const uint32_t *q, uint32_t b_bits, int sim,
+                             const ssj_options *opts, ssj_plan **out, void *hip_stream);
+
+/*
+ * ssj_plan_execute -- run a prepared join on the current tokens: one graph
+ * launch on hip_stream, then, on the host, the drain-and-resume rounds the
+ * survivor queue needs when it fills, the candidates of rows past the
+ * cutoff (SSJ_FLAG_CUTOFF), and the sort and copy of the pairs.  Output as
+ * ssj_self_join_batch: exactly the pairs the unprepared call returns for
+ * the same tokens.  Executions of one plan take turns (a lock held until
+ * the call returns); the plan's device must be current.
+ *   stats        NULL or totals; ms_prepare is 0 (planning happened once),
+ *                ms_filter includes the whole graph (bitmaps, first filter
+ *                round and its verification), class_ms only later rounds
+ * Errors: SSJ_E_INVALID (NULL plan, other device), SSJ_E_UNSORTED (tokens
+ * no longer strictly increasing), SSJ_E_NOMEM, SSJ_E_DEVICE; on any error
+ * *out = {NULL, 0}.
+ */
+int ssj_plan_execute(ssj_plan *plan, ssj_pairs *out, uint64_t *starts, ssj_stats *stats,
+                     void *hip_stream);
+
+/* Release a plan, its graph and its device memory (NULL-safe).  No
+ * execution of it may still be running. */
+void ssj_plan_destroy(ssj_plan *plan);
+
 /*
  * ssj_cutoff -- the cutoff point omega(b, t) of Section 3.5: the largest set
  * size n for which the expected normalized overlap bound of two sets of n
@@ -350,6 +401,21 @@ const char *ssj_status_string(int status);
 
 /* SSJ_ABI_VERSION of the loaded library. */
 int ssj_abi_version(void);
+
+/*
+ * ssj_memory_limit -- cap the device memory that the library's per-call
+ * working memory may hold on each device: the chunks of its cache, idle or
+ * in use by a call (a resident index's own memory is not counted).
+ *   bytes  the cap in bytes; 0 removes it.  Idle chunks beyond a new cap are
+ *          freed at once.
+ *   held   out (nullable): bytes the current device's chunks hold now.
+ * A call whose working memory would pass the cap first makes the cache free
+ * its idle chunks; when that is not enough the call fails with SSJ_E_NOMEM
+ * and returns no output (*out = {NULL, 0}).  A serving loop sets it to the
+ * budget its admission control plans with.  Freeing chunks waits for the
+ * device.  Returns SSJ_E_DEVICE when no device is current.
+ */
+int ssj_memory_limit(uint64_t bytes, uint64_t *held);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,8 @@ SSJ_NOALLOC_MAX_SETS = 4_000_000
 EXPORTS = ("ssj_build_bitmaps", "ssj_build_bitmaps_noalloc", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
            "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_cutoff",
            "ssj_free_pairs",
-           "ssj_status_string", "ssj_abi_version")
+           "ssj_status_string", "ssj_abi_version", "ssj_memory_limit",
+           "ssj_plan_self_join_batch", "ssj_plan_execute", "ssj_plan_destroy")
 
 
 class ssj_sets(ctypes.Structure):
@@ -120,6 +121,18 @@ def load() -> ctypes.CDLL:
         lib.ssj_free_pairs.restype = None
         lib.ssj_status_string.argtypes = [c_int]
         lib.ssj_status_string.restype = ctypes.c_char_p
+        lib.ssj_memory_limit.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        lib.ssj_memory_limit.restype = c_int
+        lib.ssj_plan_self_join_batch.argtypes = [sp, u32, u32p, u32p, u32, c_int,
+                                                 ctypes.POINTER(ssj_options), ctypes.POINTER(vp),
+                                                 vp]
+        lib.ssj_plan_self_join_batch.restype = c_int
+        lib.ssj_plan_execute.argtypes = [vp, ctypes.POINTER(ssj_pairs),
+                                         ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ssj_stats), vp]
+        lib.ssj_plan_execute.restype = c_int
+        lib.ssj_plan_destroy.argtypes = [vp]
+        lib.ssj_plan_destroy.restype = None
         lib.ssj_abi_version.argtypes = []
         lib.ssj_abi_version.restype = c_int
         _lib = lib
@@ -290,6 +303,50 @@ def ssj_self_join_batch(instances, p, q, b_bits: int = 0, sim: int = SSJ_SIM_JAC
     return _split(_take(out), starts, n), stats.as_dict()
 
 
+class Plan:
+    """A prepared self-join of one or more instances (ssj_plan_*): planned
+    once, its first round replayed from a HIP graph by every execute().  The
+    instances' buffers must stay alive and their offsets unchanged; the
+    tokens may change between executions."""
+
+    def __init__(self, instances, p, q, b_bits: int = 0, sim: int = SSJ_SIM_JACCARD,
+                 queue_capacity: int = 0, tile_cols: int = 0, flags: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        n, arr, pa, qa, _ = _tasks(instances, p, q)
+        self._keep = (list(instances), arr, pa, qa)
+        self.n = n
+        o = _opts(queue_capacity, tile_cols, flags)
+        st = load().ssj_plan_self_join_batch(arr, n, pa, qa, b_bits, sim,
+                                             ctypes.byref(o) if o else None,
+                                             ctypes.byref(self._h), _stream(stream))
+        if st != SSJ_OK:
+            self._h = ctypes.c_void_p()
+            raise SsjError(st, "ssj_plan_self_join_batch")
+
+    def execute(self, stream=None):
+        """Returns ([pairs of instance k], totals stats dict)."""
+        if not self._h:
+            raise RuntimeError("plan is closed")
+        out, stats = ssj_pairs(), ssj_stats()
+        starts = (ctypes.c_uint64 * (self.n + 1))()
+        st = load().ssj_plan_execute(self._h, ctypes.byref(out), starts, ctypes.byref(stats),
+                                     _stream(stream))
+        if st != SSJ_OK:
+            raise SsjError(st, "ssj_plan_execute")
+        return _split(_take(out), starts, self.n), stats.as_dict()
+
+    def close(self):
+        if self._h:
+            load().ssj_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Index:
     """A resident collection S for repeated R-S queries (ssj_index_*)."""
 
@@ -336,6 +393,17 @@ class Index:
             self.close()
         except Exception:
             pass
+
+
+def ssj_memory_limit(limit_bytes: int) -> int:
+    """Caps the device memory of the library's per-call working memory on
+    each device (0: no cap); returns the bytes the current device's chunks
+    hold now."""
+    held = ctypes.c_uint64(0)
+    st = load().ssj_memory_limit(int(limit_bytes), ctypes.byref(held))
+    if st != SSJ_OK:
+        raise SsjError(st, "ssj_memory_limit")
+    return int(held.value)
 
 
 def ssj_cutoff(b_bits: int, p: int, q: int, method: int = SSJ_BM_XOR,

@@ -13,25 +13,33 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
 
+#include "autotune_table.h"
 #include "ssj.h"
 #include "ssj_internal.h"
 
 namespace ssj {
 namespace {
 
-constexpr uint64_t kDefaultQueue = 1ull << 29;   // 4 GiB of (row, column) pairs
+// Survivor queue: a call starts with kInitialQueue entries (64 MiB of
+// (row, column) pairs, and as many result keys) unless the caller fixes
+// the capacity, and quadruples it after each round that filled it, up to
+// kMaxQueue (4 GiB): memory follows what the band's survivors need.
+constexpr uint64_t kInitialQueue = 1ull << 23;
+constexpr uint64_t kMaxQueue = 1ull << 29;
 constexpr uint32_t kDefaultTileCols = 2048;
 // A width class with fewer than about kMinSlotTiles tiles of the default
 // width gets narrower tiles, down to kMinTileCols columns; kMinTileColsValu
@@ -66,7 +74,11 @@ inline void check(hipError_t e) {
 // at its start and gives them back only after its final stream
 // synchronisation, so a chunk is never in use by two calls.  Chunk sizes are
 // powers of two (at least 64 MiB), so a chunk fits any later request of up to
-// its size.  The cache lives until the process ends.
+// its size.  The cache lives until the process ends.  An optional limit caps
+// the bytes a device's chunks hold (cached or lent): a new chunk that would
+// pass it first makes the cache free its idle chunks, and fails when that is
+// not enough.  A failed hipMalloc also frees the idle chunks and tries once
+// more.
 class ChunkCache {
  public:
   static ChunkCache &get() {
@@ -74,28 +86,47 @@ class ChunkCache {
     return c;
   }
   void *take(int dev, uint64_t size) {
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      auto &v = free_[dev & 63];
-      for (size_t k = 0; k < v.size(); ++k)
-        if (v[k].size == size) {
-          void *p = v[k].ptr;
-          v[k] = v.back();
-          v.pop_back();
-          return p;
-        }
-    }
+    std::lock_guard<std::mutex> lk(mu_);
+    const int d = dev & 63;
+    auto &v = free_[d];
+    for (size_t k = 0; k < v.size(); ++k)
+      if (v[k].size == size) {
+        void *p = v[k].ptr;
+        v[k] = v.back();
+        v.pop_back();
+        return p;
+      }
+    if (limit_ && held_[d] + size > limit_) release_idle(d);
+    if (limit_ && held_[d] + size > limit_) return nullptr;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, size);
     if (e != hipSuccess || !p) {
       (void)hipGetLastError();
-      return nullptr;
+      release_idle(d);
+      p = nullptr;
+      e = hipMalloc(&p, size);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
     }
+    held_[d] += size;
     return p;
   }
   void give(int dev, void *p, uint64_t size) {
     std::lock_guard<std::mutex> lk(mu_);
-    free_[dev & 63].push_back({p, size});
+    const int d = dev & 63;
+    free_[d].push_back({p, size});
+    if (limit_ && held_[d] > limit_) release_idle(d);
+  }
+  // Sets the limit (0: none) and returns what the current device's chunks
+  // hold; idle chunks beyond a new limit are freed.
+  uint64_t limit(uint64_t bytes, int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    limit_ = bytes;
+    const int d = dev & 63;
+    if (limit_ && held_[d] > limit_) release_idle(d);
+    return held_[d];
   }
 
  private:
@@ -103,8 +134,19 @@ class ChunkCache {
     void *ptr;
     uint64_t size;
   };
+  // Frees the idle chunks of device d (the current device).  hipFree waits
+  // for the device, so this happens only when memory runs short.
+  void release_idle(int d) {
+    for (auto &c : free_[d]) {
+      (void)hipFree(c.ptr);
+      held_[d] -= c.size;
+    }
+    free_[d].clear();
+  }
   std::mutex mu_;
   std::vector<Chunk> free_[64];
+  uint64_t held_[64] = {};
+  uint64_t limit_ = 0;
 };
 
 // Bump allocator over device memory chunks.  A call's arena takes cached
@@ -189,6 +231,33 @@ void h2d(T *dst, const T *src, uint64_t n, hipStream_t st) {
   check(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st));
 }
 void sync(hipStream_t st) { check(hipStreamSynchronize(st)); }
+
+// Device work whose inputs are the caller's tokens (bitmaps, sign planes,
+// the filter and verification of a join's first round): launched at once,
+// or recorded in order so that a prepared join can replay it from a HIP
+// graph (work that depends only on the set sizes runs when it is planned).
+class Launcher {
+ public:
+  explicit Launcher(bool record) : record_(record) {}
+  bool recording() const { return record_; }
+  void run(hipStream_t st, std::function<hipError_t(hipStream_t)> f) {
+    if (record_) ops_.push_back(std::move(f));
+    else check(f(st));
+  }
+  void replay(hipStream_t st) const {
+    for (const auto &f : ops_) check(f(st));
+  }
+
+ private:
+  bool record_;
+  std::vector<std::function<hipError_t(hipStream_t)>> ops_;
+};
+
+// Runs f on st now, or records it when L records.
+inline void go(Launcher *L, hipStream_t st, std::function<hipError_t(hipStream_t)> f) {
+  if (L) L->run(st, std::move(f));
+  else check(f(st));
+}
 
 int bits_for(uint64_t v) {
   int b = 0;
@@ -335,24 +404,32 @@ void space_finish(Space &sp) {
 // Bitmap-Xor bitmaps of every set at `words` 64-bit words (nominal width
 // `bits`), in size order.
 void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCounters *ctr,
-                   hipStream_t st) {
+                   hipStream_t st, Launcher *L = nullptr) {
   if (sp.bitmaps(words)) return;
   if (sp.n_bm >= kMaxClasses) throw Fail{SSJ_E_DEVICE};
   uint64_t *out = ar.alloc<uint64_t>(sp.n * words);
-  check(launch_build_bitmaps(sp.d_sides, sp.n_sides, sp.seg_blocks, sp.n, sp.perm, sp.rank,
-                             sp.side_of, bits, SSJ_BM_XOR, words, out, ctr, st));
+  const SideDesc *sides = sp.d_sides;
+  const uint32_t n_sides = sp.n_sides, seg = sp.seg_blocks;
+  const uint64_t n = sp.n;
+  const uint32_t *perm = sp.perm, *rank = sp.rank, *side_of = sp.side_of;
+  go(L, st, [=](hipStream_t s) {
+    return launch_build_bitmaps(sides, n_sides, seg, n, perm, rank, side_of, bits, SSJ_BM_XOR,
+                                words, out, ctr, s);
+  });
   sp.bm_words[sp.n_bm] = words;
   sp.bm[sp.n_bm] = out;
   ++sp.n_bm;
 }
 
 // Sign planes of the space's bitmaps at `words` words (built before).
-void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st) {
+void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st, Launcher *L = nullptr) {
   for (uint32_t k = 0; k < sp.n_bm; ++k) {
     if (sp.bm_words[k] != words) continue;
     if (sp.sg[k]) return;
     uint4 *planes = ar.alloc<uint4>((sp.n + kSignPad) * words * 2);
-    check(launch_expand_signs(sp.bm[k], words, sp.n, planes, st));
+    const uint64_t *bm = sp.bm[k];
+    const uint64_t n = sp.n;
+    go(L, st, [=](hipStream_t s) { return launch_expand_signs(bm, words, n, planes, s); });
     sp.sg[k] = planes;
     return;
   }
@@ -361,7 +438,7 @@ void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st) {
 
 // Wide bitmaps of every set larger than kWideMin: in size order they are a
 // suffix of each side (from its group start at kWideMin + 1).
-void space_wide(Space &sp, Arena &ar, hipStream_t st) {
+void space_wide(Space &sp, Arena &ar, hipStream_t st, Launcher *L = nullptr) {
   if (sp.wide_built) return;
   sp.wide_built = true;
   std::vector<uint32_t> lo(sp.n_sides, 0xFFFFFFFFu), slot(sp.n_sides, 0);
@@ -392,15 +469,19 @@ void space_wide(Space &sp, Arena &ar, hipStream_t st) {
   WideRange *d_ranges = ar.alloc<WideRange>(ranges.size());
   h2d(d_ranges, ranges.data(), ranges.size(), st);
   sp.bmw = ar.alloc<uint64_t>(total * kWideWords);
-  check(launch_build_wide(sp.d_sides, sp.perm, d_ranges, (uint32_t)ranges.size(), total, sp.bmw,
-                          st));
+  const SideDesc *sides = sp.d_sides;
+  const uint32_t *perm = sp.perm, n_ranges = (uint32_t)ranges.size();
+  uint64_t *bmw = sp.bmw;
+  go(L, st, [=](hipStream_t s) {
+    return launch_build_wide(sides, perm, d_ranges, n_ranges, total, bmw, s);
+  });
 }
 
 // Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to 8
 // words come from one pass over the tokens: the widest is built and the
 // narrower ones are folded from it in the same kernel.
 void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits, uint32_t n,
-                         Arena &ar, JoinCounters *ctr, hipStream_t st) {
+                         Arena &ar, JoinCounters *ctr, hipStream_t st, Launcher *L = nullptr) {
   uint32_t need_w[kMaxClasses + 1], need_b[kMaxClasses + 1], m = 0, wmax = 0;
   bool foldable = sp.rank != nullptr;
   for (uint32_t k = 0; k < n; ++k) {
@@ -414,7 +495,7 @@ void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits,
   }
   if (m == 0) return;
   if (!foldable || m == 1 || sp.n_bm + m > kMaxClasses) {
-    for (uint32_t k = 0; k < m; ++k) space_bitmaps(sp, need_w[k], need_b[k], ar, ctr, st);
+    for (uint32_t k = 0; k < m; ++k) space_bitmaps(sp, need_w[k], need_b[k], ar, ctr, st, L);
     return;
   }
   FoldOut fold{{nullptr, nullptr, nullptr}};
@@ -431,8 +512,15 @@ void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits,
     sp.bm[sp.n_bm] = dst;
     ++sp.n_bm;
   }
-  check(launch_build_bitmaps(sp.d_sides, sp.n_sides, sp.seg_blocks, sp.n, sp.perm, sp.rank,
-                             sp.side_of, 64 * wmax, SSJ_BM_XOR, wmax, widest, ctr, st, &fold));
+  const SideDesc *sides = sp.d_sides;
+  const uint32_t n_sides = sp.n_sides, seg = sp.seg_blocks;
+  const uint64_t nn = sp.n;
+  const uint32_t *perm = sp.perm, *rank = sp.rank, *side_of = sp.side_of;
+  go(L, st, [=](hipStream_t s) {
+    FoldOut f = fold;
+    return launch_build_bitmaps(sides, n_sides, seg, nn, perm, rank, side_of, 64 * wmax,
+                                SSJ_BM_XOR, wmax, widest, ctr, s, &f);
+  });
 }
 
 // The caller's bitmaps of a one-side space (caller order, bits/64 words),
@@ -528,12 +616,16 @@ double binomial_cdf(int n, double pi, int64_t k) {
 // unrelated sets differ as Binomial(b, pi) with pi = (1 - (1 - 2/b)^L) / 2,
 // the chance that a bit receives an odd number of the L tokens (the quantity
 // Eq. 5 sums; Section 3.4).  A pair is a false survivor when that count is at
-// most slack(L).  Per row size the width minimising
-//   (b/16 + 1)  +  P(false survivor) * kSurvivorCost
-// lane-ops per band pair is chosen, b in {64, 128, 256, 512}; widths never
-// decrease with the size.  kSurvivorCost prices a survivor (queue slot,
-// slow path, verification) in filter lane-ops.
-constexpr double kSurvivorCost = 3000.0;
+// most slack(L).  With the costs measured on the GPU (calibrate.py writes
+// them to autotune_table.h) -- the filter's time per band pair at each width,
+// the time a survivor costs (the filter's slow path and queue writes, and its
+// verification), and the fixed cost of a width class's launch -- the widths
+// b(a), b in {64, 128, 256, 512} and never decreasing with the size, are the
+// ones that minimise the task's expected time
+//   sum over row sizes a of  band(a) * (filter(b(a)) + P(false survivor) * survivor(b(a)))
+//   + the launch cost of every width used,
+// band(a) being the task's band pairs of rows of size a.  A dynamic program
+// over the sizes finds them.
 constexpr uint32_t kAutoWords[4] = {1, 2, 4, 8};  // b = 64, 128, 256, 512
 
 struct WidthClass {
@@ -541,49 +633,97 @@ struct WidthClass {
   uint32_t words;
 };
 
-// The width of every row size up to max_rows, in classes of consecutive
-// sizes.  The per-size choice depends only on the threshold, so it is kept
-// per threshold and extended as larger sizes come up.
-std::vector<WidthClass> choose_classes(uint32_t max_rows, int sim, uint64_t p, uint64_t q) {
+// P(false survivor) of a row of size a at each automatic width, per
+// (function, threshold), extended as larger sizes come up.
+std::vector<std::array<double, 4>> false_survivor_odds(uint32_t max_rows, int sim, uint64_t p,
+                                                       uint64_t q) {
   static std::mutex mu;
-  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>, std::vector<uint8_t>> memo;
-  std::vector<uint8_t> wa;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    std::vector<uint8_t> &w = memo[{sim, {p, q}}];  // w[a]: words for row size a; w[0] unused
-    if (w.empty()) w.push_back((uint8_t)kAutoWords[0]);
-    uint32_t cur = w.back();
-    const uint32_t upto = std::max<uint32_t>(max_rows, 1);
-    for (uint32_t a = (uint32_t)w.size(); a <= upto; ++a) {
-      if (cur != kAutoWords[3]) {
-        const uint64_t L = 2ull * a;
-        const int64_t slack = (int64_t)L - 2 * (int64_t)omin_of(sim, a, a, p, q);
-        uint32_t best = cur;
-        double best_cost = 1e300;
-        for (uint32_t wd : kAutoWords) {
-          if (wd < cur) continue;
-          const double b = 64.0 * wd;
-          const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
-          const double cost = (b / 16 + 1) + binomial_cdf((int)b, pi, slack) * kSurvivorCost;
-          if (cost < best_cost) {
-            best_cost = cost;
-            best = wd;
-          }
-        }
-        cur = best;
-      }
-      w.push_back((uint8_t)cur);
+  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>,
+                  std::vector<std::array<double, 4>>> memo;
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<std::array<double, 4>> &v = memo[{sim, {p, q}}];
+  if (v.empty()) v.push_back({0.0, 0.0, 0.0, 0.0});  // size 0: never pairs
+  for (uint32_t a = (uint32_t)v.size(); a <= max_rows; ++a) {
+    const uint64_t L = 2ull * a;
+    const int64_t slack = (int64_t)L - 2 * (int64_t)omin_of(sim, a, a, p, q);
+    std::array<double, 4> pr{};
+    for (int k = 0; k < 4; ++k) {
+      const double b = 64.0 * kAutoWords[k];
+      const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
+      pr[k] = binomial_cdf((int)b, pi, slack);
     }
-    wa.assign(w.begin(), w.begin() + upto + 1);
+    v.push_back(pr);
+  }
+  return std::vector<std::array<double, 4>>(v.begin(), v.begin() + max_rows + 1);
+}
+
+// The width classes of a task whose rows of size a hold band[a] band pairs
+// (a = 0 .. band.size() - 1).
+std::vector<WidthClass> choose_classes(const std::vector<double> &band, int sim, uint64_t p,
+                                       uint64_t q) {
+  const uint32_t n = std::max<uint32_t>((uint32_t)band.size() - 1, 1);
+  const auto odds = false_survivor_odds(n, sim, p, q);
+  // best[a][k]: least cost of sizes 1..a with size a at width k
+  std::vector<std::array<double, 4>> best(n + 1);
+  std::vector<std::array<int8_t, 4>> from(n + 1);
+  for (uint32_t a = 1; a <= n; ++a) {
+    const double w = a < band.size() ? band[a] : 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const double here = w * (kFilterNsPerPair[k] + odds[a][k] * kSurvivorNs);
+      if (a == 1) {
+        best[a][k] = here + kClassLaunchNs[k];
+        from[a][k] = (int8_t)k;
+        continue;
+      }
+      double b = best[a - 1][k];
+      int8_t f = (int8_t)k;
+      for (int j = 0; j < k; ++j)
+        if (best[a - 1][j] + kClassLaunchNs[k] < b) {
+          b = best[a - 1][j] + kClassLaunchNs[k];
+          f = (int8_t)j;
+        }
+      best[a][k] = here + b;
+      from[a][k] = f;
+    }
+  }
+  int k = 0;
+  for (int j = 1; j < 4; ++j)
+    if (best[n][j] < best[n][k]) k = j;
+  std::vector<uint32_t> width(n + 1, kAutoWords[0]);
+  for (uint32_t a = n; a >= 1; --a) {
+    width[a] = kAutoWords[k];
+    k = from[a][k];
   }
   std::vector<WidthClass> cls;
-  for (uint32_t a = 1; a <= max_rows; ++a) {
-    if (!cls.empty() && cls.back().words == wa[a]) cls.back().max_size = a;
-    else cls.push_back({a, wa[a]});
+  for (uint32_t a = 1; a <= n; ++a) {
+    if (!cls.empty() && cls.back().words == width[a]) cls.back().max_size = a;
+    else cls.push_back({a, width[a]});
   }
-  if (cls.empty()) cls.push_back({max_rows, wa[1]});
-  cls.back().max_size = max_rows;
   return cls;
+}
+
+// Band pairs of a task's rows of each size (Table 2's length band; a
+// self-join counts each unordered pair once, same-size pairs included).
+std::vector<double> band_by_size(const Space &R, const Space &C, int sim, uint64_t p, uint64_t q,
+                                 uint32_t row_side, uint32_t col_side, bool self) {
+  const uint32_t a_max = R.side_max[row_side], c_max = C.side_max[col_side];
+  const uint32_t *rs = R.ss(row_side), *cs = C.ss(col_side);
+  std::vector<double> w((size_t)a_max + 1, 0.0);
+  for (uint32_t a = 1; a <= a_max; ++a) {
+    const double nr = (double)rs[a + 1] - (double)rs[a];
+    if (nr <= 0) continue;
+    uint64_t lo = 0, hi = 0;
+    size_band(sim, a, p, q, lo, hi);
+    hi = std::min<uint64_t>(hi, c_max);
+    if (self) hi = std::min<uint64_t>(hi, a);
+    if (lo > hi) continue;
+    if (self && hi == a) {
+      w[a] = nr * ((double)cs[a] - (double)cs[lo]) + nr * (nr - 1) / 2;
+    } else {
+      w[a] = nr * ((double)cs[hi + 1] - (double)cs[lo]);
+    }
+  }
+  return w;
 }
 
 // ------------------------------------------------------------ cutoff point
@@ -845,7 +985,8 @@ struct JoinConfig {
   uint32_t b_bits = 0;         // 0: width classes chosen per task
   uint32_t tile_cols = kDefaultTileCols;
   bool tile_cols_fixed = false;  // the caller chose tile_cols
-  uint64_t cap = kDefaultQueue;
+  uint64_t cap = kInitialQueue;
+  bool cap_fixed = false;       // the caller chose the queue capacity
   bool survivors_only = false;
   bool cutoff = false;         // rows past the cutoff point take prefix-filtered candidates
   bool cols_resident = false;  // the column space is an index's
@@ -853,15 +994,108 @@ struct JoinConfig {
   bool mfma_always = false;    // ... for every width class, whatever its band pairs
 };
 
-// Plans and runs the tasks over prepared spaces R (rows) and C (columns; C
-// may be R), whose caller bitmaps, if any, are already in place.  Fills jo
-// and the stats (except ms_total and ms_prepare's start).
-void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinConfig &jc,
-              Arena &ar, JoinCounters *ctr, hipStream_t st, Timer &t_prep, JoinOut &jo,
-              ssj_stats *stats) {
+// What a join keeps between its first round and its end: the plan, its
+// device copies and its buffers.  A prepared join keeps them across
+// executions; join_end works on copies of what a round changes.
+struct JoinRun {
+  Space *R = nullptr, *C = nullptr;
+  std::vector<TaskIn> tasks;
+  JoinConfig jc;
+  bool automatic = false, any_cosine = false;
+  uint32_t n_tasks = 0;
+  Plan pl;
+  JoinCounters *ctr = nullptr;
+  const RowBlock *d_blocks = nullptr;
+  const TaskDesc *d_tasks = nullptr;
+  const uint32_t *d_side_task = nullptr, *d_tables = nullptr;
+  uint32_t *d_tile_block = nullptr;
+  uint64_t qcap = 0;
+  uint32_t dense_chunk = 0;
+  uint2 *queue = nullptr;
+  Resume *res_a = nullptr, *res_b = nullptr;
+  uint64_t res_cap = 0;
+  unsigned long long *results = nullptr;
+  int ib = 1, jb = 1, tb = 0;
+  uint32_t w2 = 0;
+  VerifySpace vrows{}, vcols{};
+  FilterConfig cfg{};
+  std::vector<PrefixRun> runs;    // rows past the cutoff
+  std::vector<uint32_t> ilen;
+  uint64_t n_probe = 0;
+};
+
+// Kernel timings of a join's rounds (events must not move).
+struct RoundTimes {
+  std::deque<Timer> filter, verify;
+  std::vector<uint32_t> filter_slot;
+  uint32_t launches = 0;
+  hipEvent_t graph_ev[2] = {nullptr, nullptr};  // around a prepared join's graph
+};
+
+// One filter/verify round: a filter launch per width slot, then the
+// verification of the queue.  Timed when tm is given (L then runs at once).
+void launch_round(const JoinRun &jr, FilterConfig cfg, uint2 *queue, uint64_t qcap,
+                  uint32_t dense_chunk, Resume *rin, Resume *rout, unsigned long long *results,
+                  uint64_t res_cap, hipStream_t st, Launcher *L, RoundTimes *tm) {
+  const Plan &pl = jr.pl;
+  const Space &R = *jr.R, &C = *jr.C;
+  cfg.cap = qcap;
+  // one launch per width slot; after an overflow the later launches of
+  // the round leave at once and resume in the next round
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    if (pl.tile_hi[k] == pl.tile_lo[k]) continue;
+    cfg.tile_lo = pl.tile_lo[k];
+    cfg.tile_hi = pl.tile_hi[k];
+    cfg.tile_cols = pl.slot_tile_cols[k];
+    cfg.cls = k;
+    cfg.chunk = jr.automatic && pl.slot_words[k] < kAutoWords[3] ? kFilterStage : dense_chunk;
+    const uint32_t w = pl.slot_words[k];
+    const bool mf = pl.slot_mfma[k], cos = jr.any_cosine;
+    const FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
+                        mf ? C.signs(w) : nullptr, R.sizes, C.sizes, C.sstart, jr.d_tables,
+                        jr.d_tasks, jr.d_blocks, jr.d_tile_block, queue, jr.ctr, rin, rout, cfg};
+    if (tm) {
+      tm->filter.emplace_back();
+      tm->filter_slot.push_back(k);
+      ++tm->launches;
+      check(hipEventRecord(tm->filter.back().ev[0], st));
+    }
+    go(L, st, [=](hipStream_t s) { return launch_filter(w, cos, fa, s); });
+    if (tm) check(hipEventRecord(tm->filter.back().ev[1], st));
+  }
+  if (tm) {
+    tm->verify.emplace_back();
+    check(hipEventRecord(tm->verify.back().ev[0], st));
+  }
+  const VerifySpace vr = jr.vrows, vc = jr.vcols;
+  const uint32_t *side_task = jr.d_side_task, *tables = jr.d_tables, w2 = jr.w2;
+  const TaskDesc *tasks = jr.d_tasks;
+  const int ib = jr.ib, jb = jr.jb;
+  const uint32_t so = jr.jc.survivors_only ? 1u : 0u;
+  JoinCounters *ctr = jr.ctr;
+  go(L, st, [=](hipStream_t s) {
+    return launch_verify(queue, qcap, vr, vc, side_task, tasks, tables, ib, jb, so, w2, results,
+                         res_cap, ctr, s);
+  });
+  if (tm) check(hipEventRecord(tm->verify.back().ev[1], st));
+}
+
+// Plans the tasks over prepared spaces R (rows) and C (columns; C may be
+// R), whose caller bitmaps, if any, are already in place, and starts the
+// first filter/verify round.  Device work that reads the tokens goes
+// through L (nullptr: at once); work that depends only on the set sizes
+// (the plan's upload, the tile list) runs at once.
+void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinConfig &jc,
+                Arena &ar, JoinCounters *ctr, hipStream_t st, Timer *t_prep, Launcher *L,
+                RoundTimes *tm, JoinRun &jr) {
+  jr.R = &R;
+  jr.C = &C;
+  jr.tasks = tasks;
+  jr.jc = jc;
+  jr.ctr = ctr;
   const bool automatic = jc.b_bits == 0;
   const uint32_t n_tasks = (uint32_t)tasks.size();
-  Plan pl;
+  Plan &pl = jr.pl;
   pl.mfma = jc.mfma;
   pl.tasks.resize(n_tasks);
   std::vector<std::vector<WidthClass>> classes(n_tasks);
@@ -883,7 +1117,9 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     td.self = tk.self ? 1u : 0u;
     td.col_sstart_off = (uint64_t)tk.col_side * C.stride;
     if (automatic)
-      classes[k] = choose_classes(std::max<uint32_t>(a_max, 1), tk.sim, tk.p, tk.q);
+      classes[k] = choose_classes(
+          band_by_size(R, C, tk.sim, tk.p, tk.q, tk.row_side, tk.col_side, tk.self), tk.sim,
+          tk.p, tk.q);
     else classes[k].push_back({a_max, wpad});
   }
   // The cutoff point (Section 3.5) of every task at its widest width: rows
@@ -961,31 +1197,38 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   for (uint32_t k = 0; k < nbw; ++k) {
     if (jc.cols_resident && !C.bitmaps(bw[k])) throw Fail{SSJ_E_UNSUPPORTED};
   }
-  space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st);
-  if (!jc.cols_resident) space_bitmaps_multi(C, bw, bb, nbw, ar, ctr, st);
+  space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st, L);
+  if (!jc.cols_resident) space_bitmaps_multi(C, bw, bb, nbw, ar, ctr, st, L);
   // sign planes for the widths the matrix-core kernel runs (an index holds
   // its own)
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     const uint32_t w = pl.slot_words[k];
     if (!pl.slot_mfma[k]) continue;
-    space_signs(R, w, ar, st);
+    space_signs(R, w, ar, st, L);
     if (jc.cols_resident) {
       if (!C.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
     } else {
-      space_signs(C, w, ar, st);
+      space_signs(C, w, ar, st, L);
     }
   }
   if (pl.n_slots == 0) {
     // no bitmaps (every row past the cutoff): check the token order directly
-    for (const auto &d : R.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
+    for (const auto &d : R.h_sides)
+      go(L, st, [=](hipStream_t s) { return launch_check_sorted(d.offsets, d.tokens, d.n, ctr, s); });
     if (&C != &R && !jc.cols_resident)
-      for (const auto &d : C.h_sides) check(launch_check_sorted(d.offsets, d.tokens, d.n, ctr, st));
+      for (const auto &d : C.h_sides)
+        go(L, st, [=](hipStream_t s) { return launch_check_sorted(d.offsets, d.tokens, d.n, ctr, s); });
   }
   // tiles, slot by slot, task by task.  Unless the caller fixed the tile
   // width, a slot with little work gets narrower tiles, so that it is cut
   // into enough tiles to occupy every wave of the GPU.
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     uint32_t tile_cols = jc.tile_cols;
+    if (!jc.tile_cols_fixed && automatic) {
+      // the measured best tile width of the class's width
+      for (int a = 0; a < 4; ++a)
+        if (kAutoWords[a] == pl.slot_words[k]) tile_cols = kClassTileCols[a];
+    }
     if (!jc.tile_cols_fixed) {
       const FilterShape shape = filter_shape(pl.slot_words[k], pl.slot_mfma[k]);
       const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * kMinSlotTiles);
@@ -1011,9 +1254,9 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   }
 
   // rows past the cutoff: their band pairs, probe runs and prefix lengths
-  std::vector<PrefixRun> runs;
-  std::vector<uint32_t> ilen;  // [column side][size]: prefix length indexed (0: none)
-  uint64_t n_probe = 0;
+  std::vector<PrefixRun> &runs = jr.runs;
+  std::vector<uint32_t> &ilen = jr.ilen;  // [column side][size]: prefix length indexed (0: none)
+  uint64_t &n_probe = jr.n_probe;
   for (uint32_t k = 0; k < n_tasks; ++k) {
     if (omega[k] == 0xFFFFFFFFu) continue;
     const TaskIn &tk = tasks[k];
@@ -1083,7 +1326,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   const uint32_t *d_tables = d_side_task + nS;
   uint32_t *d_tile_block = ar.alloc<uint32_t>(pl.n_tiles);
   check(launch_expand_tiles(d_blocks, (uint32_t)nB, pl.n_tiles, d_tile_block, st));
-  check(hipEventRecord(t_prep.ev[1], st));
+  if (t_prep) check(hipEventRecord(t_prep->ev[1], st));
 
   // filter / verify rounds.  A wave reserves queue slots a chunk at a time
   // and writes staged runs (at most kFilterStage pairs) into its chunk; the
@@ -1097,8 +1340,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   // the others, where the bits saturate) and a fixed width can keep many
   // pairs, and their waves take up to 1024.
   static_assert(kFilterStage <= 4096, "the queue holds at least 4096 entries");
-  const uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
-  const uint32_t dense_chunk =
+  uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
+  uint32_t dense_chunk =
       (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
   uint2 *queue = ar.alloc<uint2>(qcap);
   const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
@@ -1120,8 +1363,8 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
   // wide bitmaps for pairs of large sets (automatic mode, as the cascade);
   // an index holds its own
   if (cascade) {
-    space_wide(R, ar, st);
-    if (!jc.cols_resident) space_wide(C, ar, st);
+    space_wide(R, ar, st, L);
+    if (!jc.cols_resident) space_wide(C, ar, st, L);
   }
   const bool wide = cascade && R.bmw && C.bmw;
   const VerifySpace vrows{R.d_sides, R.side_of, R.perm, R.sizes, cascade ? R.bitmaps(w2) : nullptr,
@@ -1130,69 +1373,102 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
                           (uint32_t)C.n, wide ? C.bmw : nullptr, C.wide_lo, C.wide_slot};
   if (!cascade) w2 = 0;
 
-  std::deque<Timer> t_filter, t_verify;  // events must not move
-  float prefix_ms_index = 0, prefix_ms_verify = 0;
-  uint64_t prefix_candidates = 0;
-  std::vector<uint32_t> t_filter_slot;
-  uint32_t n_resume_in = 0;
-  uint64_t results_n = 0;
-  JoinCounters ctr_h{};
-  FilterConfig cfg{};
+
+  jr.automatic = automatic;
+  jr.any_cosine = any_cosine;
+  jr.n_tasks = n_tasks;
+  jr.d_blocks = d_blocks;
+  jr.d_tasks = d_tasks;
+  jr.d_side_task = d_side_task;
+  jr.d_tables = d_tables;
+  jr.d_tile_block = d_tile_block;
+  jr.qcap = qcap;
+  jr.dense_chunk = dense_chunk;
+  jr.queue = queue;
+  jr.res_a = res_a;
+  jr.res_b = res_b;
+  jr.res_cap = res_cap;
+  jr.results = results;
+  jr.ib = ib;
+  jr.jb = jb;
+  jr.tb = tb;
+  jr.w2 = w2;
+  jr.vrows = vrows;
+  jr.vcols = vcols;
+  FilterConfig &cfg = jr.cfg;
+  cfg = FilterConfig{};
   cfg.n_rows = (uint32_t)R.n;
   cfg.n_cols = (uint32_t)C.n;
   cfg.n_tiles = pl.n_tiles;
-
   cfg.n_blocks = (uint32_t)nB;
   cfg.resume_cap = max_waves;
   cfg.cap = qcap;
-  for (;;) {
-    if (pl.n_tiles == 0) break;
-    cfg.n_resume_in = n_resume_in;
-    // one launch per width slot; after an overflow the later launches of
-    // the round leave at once and resume in the next round
-    for (uint32_t k = 0; k < pl.n_slots; ++k) {
-      if (pl.tile_hi[k] == pl.tile_lo[k]) continue;
-      cfg.tile_lo = pl.tile_lo[k];
-      cfg.tile_hi = pl.tile_hi[k];
-      cfg.tile_cols = pl.slot_tile_cols[k];
-      cfg.cls = k;
-      cfg.chunk = automatic && pl.slot_words[k] < kAutoWords[3] ? kFilterStage : dense_chunk;
-      const uint32_t w = pl.slot_words[k];
-      const bool mf = pl.slot_mfma[k];
-      FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
-                    mf ? C.signs(w) : nullptr, R.sizes, C.sizes, C.sstart, d_tables, d_tasks,
-                    d_blocks, d_tile_block, queue, ctr, res_a, res_b, cfg};
-      t_filter.emplace_back();
-      t_filter_slot.push_back(k);
-      check(hipEventRecord(t_filter.back().ev[0], st));
-      check(launch_filter(w, any_cosine, fa, st));
-      check(hipEventRecord(t_filter.back().ev[1], st));
+  cfg.n_resume_in = 0;
+  if (pl.n_tiles)
+    launch_round(jr, cfg, queue, qcap, dense_chunk, res_a, res_b, results, res_cap, st, L, tm);
+}
+
+// Finishes a join whose first round join_begin (or a prepared join's graph)
+// started: drains and resumes the filter while the queue fills, verifies
+// the prefix-filtered candidates of rows past the cutoff, sorts the
+// result keys and copies the pairs out.  Temporaries come from ar.
+void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Timer *t_prep,
+              JoinOut &jo, ssj_stats *stats) {
+  const Space &R = *jr.R, &C = *jr.C;
+  const Plan &pl = jr.pl;
+  const JoinConfig &jc = jr.jc;
+  const uint32_t n_tasks = jr.n_tasks;
+  JoinCounters *ctr = jr.ctr;
+  const TaskDesc *d_tasks = jr.d_tasks;
+  const uint32_t *d_side_task = jr.d_side_task, *d_tables = jr.d_tables;
+  const int ib = jr.ib, jb = jr.jb, tb = jr.tb;
+  const uint32_t w2 = jr.w2;
+  const VerifySpace &vrows = jr.vrows, &vcols = jr.vcols;
+  const std::vector<PrefixRun> &runs = jr.runs;
+  const std::vector<uint32_t> &ilen = jr.ilen;
+  const uint64_t n_probe = jr.n_probe;
+  // what a round may change: a prepared join's own buffers stay as planned
+  uint64_t qcap = jr.qcap;
+  uint32_t dense_chunk = jr.dense_chunk;
+  uint2 *queue = jr.queue;
+  Resume *res_a = jr.res_a, *res_b = jr.res_b;
+  uint64_t res_cap = jr.res_cap;
+  unsigned long long *results = jr.results;
+  FilterConfig cfg = jr.cfg;
+  float prefix_ms_index = 0, prefix_ms_verify = 0;
+  uint64_t prefix_candidates = 0;
+  uint64_t results_n = 0;
+  JoinCounters ctr_h{};
+  if (pl.n_tiles) {
+    for (;;) {
+      d2h(&ctr_h, ctr, 1, st);
+      sync(st);
+      if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+      results_n = ctr_h.results;
+      if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
+      if (!ctr_h.overflow) break;
+      // drain done; a queue the library sized itself grows for the next round
+      if (!jc.cap_fixed && qcap < std::min<uint64_t>(kMaxQueue, pl.band_pairs + 1)) {
+        qcap = std::min<uint64_t>(std::min<uint64_t>(kMaxQueue, pl.band_pairs + 1), 4 * qcap);
+        queue = ar.alloc<uint2>(qcap);
+        dense_chunk =
+            (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
+      }
+      // make room for another full queue of results, then resume
+      if (results_n + qcap > res_cap) {
+        const uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
+        unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
+        check(launch_copy_u64(results, results_n, nr, st));
+        results = nr;
+        res_cap = ncap;
+      }
+      cfg.n_resume_in = ctr_h.n_resume;
+      std::swap(res_a, res_b);
+      check(launch_reset_round(ctr, st));
+      launch_round(jr, cfg, queue, qcap, dense_chunk, res_a, res_b, results, res_cap, st, nullptr,
+                   &tm);
     }
-    t_verify.emplace_back();
-    check(hipEventRecord(t_verify.back().ev[0], st));
-    check(launch_verify(queue, qcap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
-                        jc.survivors_only ? 1u : 0u, w2, results, res_cap, ctr,
-                        st));
-    check(hipEventRecord(t_verify.back().ev[1], st));
-    d2h(&ctr_h, ctr, 1, st);
-    sync(st);
-    if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
-    results_n = ctr_h.results;
-    if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
-    if (!ctr_h.overflow) break;
-    // drain done; make room for another full queue of results, then resume
-    if (results_n + qcap > res_cap) {
-      const uint64_t ncap = std::max<uint64_t>(2 * res_cap, results_n + qcap);
-      unsigned long long *nr = ar.alloc<unsigned long long>(ncap);
-      check(launch_copy_u64(results, results_n, nr, st));
-      results = nr;
-      res_cap = ncap;
-    }
-    n_resume_in = ctr_h.n_resume;
-    std::swap(res_a, res_b);
-    check(launch_reset_round(ctr, st));
-  }
-  if (pl.n_tiles == 0) {
+  } else {
     // nothing to filter; still report unsorted input
     d2h(&ctr_h, ctr, 1, st);
     sync(st);
@@ -1313,7 +1589,7 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     stats->band_pairs = pl.band_pairs;
     stats->survivors = ctr_h.survivors;
     stats->results = results_n;
-    stats->filter_launches = (uint32_t)t_filter.size();
+    stats->filter_launches = tm.launches;
     stats->b_bits = jc.b_bits;
     stats->filter_ops = pl.filter_ops;
     stats->n_classes = pl.n_slots;
@@ -1322,13 +1598,16 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
       stats->class_max_size[k] = pl.slot_max_size[k];
       stats->class_ops[k] = pl.ops[k];
     }
-    stats->ms_prepare = t_prep.ms();
-    for (size_t k = 0; k < t_filter.size(); ++k) {
-      const float ms = t_filter[k].ms();
+    stats->ms_prepare = t_prep ? t_prep->ms() : 0.f;
+    float gms = 0;
+    if (tm.graph_ev[0]) (void)hipEventElapsedTime(&gms, tm.graph_ev[0], tm.graph_ev[1]);
+    stats->ms_filter = gms;
+    for (size_t k = 0; k < tm.filter.size(); ++k) {
+      const float ms = tm.filter[k].ms();
       stats->ms_filter += ms;
-      stats->class_ms[t_filter_slot[k]] += ms;
+      stats->class_ms[tm.filter_slot[k]] += ms;
     }
-    for (auto &t : t_verify) stats->ms_verify += t.ms();
+    for (auto &t : tm.verify) stats->ms_verify += t.ms();
     // prefix-filtered rows: index and probe count as filtering, the
     // deduplication and verification of their candidates as verification
     stats->ms_filter += prefix_ms_index;
@@ -1336,6 +1615,17 @@ void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinCo
     (void)prefix_candidates;
     stats->ms_emit = t_emit.ms();
   }
+}
+
+
+// Plans and runs the tasks at once: join_begin, then join_end.
+void run_join(Space &R, Space &C, const std::vector<TaskIn> &tasks, const JoinConfig &jc,
+              Arena &ar, JoinCounters *ctr, hipStream_t st, Timer &t_prep, JoinOut &jo,
+              ssj_stats *stats) {
+  JoinRun jr;
+  RoundTimes tm;
+  join_begin(R, C, tasks, jc, ar, ctr, st, &t_prep, nullptr, &tm, jr);
+  join_end(jr, ar, st, tm, &t_prep, jo, stats);
 }
 
 // Checks and reduces a threshold: 1 <= p <= q, except Overlap (o >= p/q),
@@ -1356,7 +1646,10 @@ JoinConfig config_of(uint32_t b_bits, const ssj_options *opts) {
     jc.tile_cols = opts->tile_cols;
     jc.tile_cols_fixed = true;
   }
-  if (opts && opts->queue_capacity) jc.cap = opts->queue_capacity;
+  if (opts && opts->queue_capacity) {
+    jc.cap = opts->queue_capacity;
+    jc.cap_fixed = true;
+  }
   jc.survivors_only = opts && (opts->flags & SSJ_FLAG_SURVIVORS_ONLY);
   jc.cutoff = opts && (opts->flags & SSJ_FLAG_CUTOFF);
   jc.mfma = !(opts && (opts->flags & SSJ_FLAG_VALU));
@@ -1439,6 +1732,31 @@ struct ssj_index {
   uint32_t b_bits = 0;
   int device = 0;
   explicit ssj_index(hipStream_t st) : ar(st, true) {}
+};
+
+// A prepared join: its plan and buffers in memory it owns, and the graph of
+// its first round.  jr points into S, so a plan never moves.
+struct ssj_plan {
+  ssj::Arena ar;
+  ssj::Space S;
+  ssj::JoinRun jr;
+  hipStream_t cap_stream = nullptr;  // capture happens on a stream of the plan's own
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::mutex mu;                     // executions take turns
+  int device = 0;
+  uint32_t n_tasks = 0;
+  explicit ssj_plan(hipStream_t st) : ar(st, true) {}
+  ssj_plan(const ssj_plan &) = delete;
+  ssj_plan &operator=(const ssj_plan &) = delete;
+  ~ssj_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace ssj {
@@ -1582,6 +1900,17 @@ ScratchSlot g_scratch[kScratchDevices];
 extern "C" {
 
 int ssj_abi_version(void) { return SSJ_ABI_VERSION; }
+
+int ssj_memory_limit(uint64_t bytes, uint64_t *held) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return SSJ_E_DEVICE;
+  }
+  const uint64_t h = ssj::ChunkCache::get().limit(bytes, dev);
+  if (held) *held = h;
+  return SSJ_OK;
+}
 
 const char *ssj_status_string(int status) {
   switch (status) {
@@ -1750,6 +2079,114 @@ int ssj_index_query(ssj_index *idx, const ssj_sets *batches, uint32_t n_batches,
 }
 
 void ssj_index_destroy(ssj_index *idx) { delete idx; }
+
+int ssj_plan_self_join_batch(const ssj_sets *sets, uint32_t n_instances, const uint32_t *p,
+                             const uint32_t *q, uint32_t b_bits, int sim,
+                             const ssj_options *opts, ssj_plan **out, void *hip_stream) {
+  using namespace ssj;
+  if (!out) return SSJ_E_INVALID;
+  *out = nullptr;
+  if (n_instances == 0 || !sets || !p || !q) return SSJ_E_INVALID;
+  ssj_plan *plan = nullptr;
+  try {
+    const JoinConfig jc = config_of(b_bits, opts);
+    std::vector<TaskIn> tasks(n_instances);
+    std::vector<const ssj_sets *> sides(n_instances);
+    for (uint32_t k = 0; k < n_instances; ++k) {
+      uint32_t pk = p[k], qk = q[k];
+      check_threshold(sim, pk, qk);
+      tasks[k] = {k, k, sim, pk, qk, true};
+      sides[k] = sets + k;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    plan = new ssj_plan(st);
+    check(hipGetDevice(&plan->device));
+    plan->n_tasks = n_instances;
+    check(hipEventCreate(&plan->ev[0]));
+    check(hipEventCreate(&plan->ev[1]));
+    JoinCounters *ctr = plan->ar.alloc<JoinCounters>(1);
+    check(launch_reset_all(ctr, st));
+    {
+      Arena tmp(st);  // the size sort's temporaries
+      space_begin(plan->S, sides.data(), n_instances, plan->ar, st);
+      sync(st);
+      space_sort(plan->S, true, plan->ar, tmp, st);
+      sync(st);
+      space_finish(plan->S);
+    }
+    // every execution starts from zeroed counters and cursors
+    Launcher L(true);
+    L.run(st, [=](hipStream_t s) { return launch_reset_all(ctr, s); });
+    join_begin(plan->S, plan->S, tasks, jc, plan->ar, ctr, st, nullptr, &L, nullptr, plan->jr);
+    sync(st);
+    // the recorded work, captured on the plan's own stream (the legacy
+    // default stream cannot be captured), at the default priority
+    check(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    check(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      L.replay(plan->cap_stream);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(plan->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    check(hipStreamEndCapture(plan->cap_stream, &plan->graph));
+    check(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+  } catch (const Fail &f) {
+    (void)hipGetLastError();
+    delete plan;
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    delete plan;
+    return SSJ_E_NOMEM;
+  }
+  *out = plan;
+  return SSJ_OK;
+}
+
+int ssj_plan_execute(ssj_plan *plan, ssj_pairs *out, uint64_t *starts, ssj_stats *stats,
+                     void *hip_stream) {
+  using namespace ssj;
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!out) return SSJ_E_INVALID;
+  clear_out(out, stats);
+  if (!plan) return SSJ_E_INVALID;
+  std::lock_guard<std::mutex> lk(plan->mu);
+  JoinOut jo;
+  try {
+    int dev = 0;
+    check(hipGetDevice(&dev));
+    if (dev != plan->device) return SSJ_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    Arena tmp(st);  // drain rounds and the result sort
+    RoundTimes tm;
+    tm.graph_ev[0] = plan->ev[0];
+    tm.graph_ev[1] = plan->ev[1];
+    check(hipEventRecord(plan->ev[0], st));
+    check(hipGraphLaunch(plan->exec, st));
+    check(hipEventRecord(plan->ev[1], st));
+    join_end(plan->jr, tmp, st, tm, nullptr, jo, stats);
+  } catch (const Fail &f) {
+    std::free(jo.pairs);
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    std::free(jo.pairs);
+    return SSJ_E_NOMEM;
+  }
+  out->pairs = jo.pairs;
+  out->count = jo.count;
+  if (starts) {
+    if (jo.task_start.size() == (size_t)plan->n_tasks + 1)
+      std::memcpy(starts, jo.task_start.data(), ((size_t)plan->n_tasks + 1) * 8);
+    else std::memset(starts, 0, ((size_t)plan->n_tasks + 1) * 8);
+  }
+  if (stats) stats->ms_total = ms_since(t_start);
+  return SSJ_OK;
+}
+
+void ssj_plan_destroy(ssj_plan *plan) { delete plan; }
 
 int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uint32_t *out) {
   using namespace ssj;

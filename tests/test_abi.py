@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version_and_status_strings():
-    assert ssj.ssj_abi_version() == 2
+    assert ssj.ssj_abi_version() == 3
     assert ssj.status_string(0) == "ok"
     assert "strictly increasing" in ssj.status_string(ssj.SSJ_E_UNSORTED)
     assert ssj.status_string(12345) == "unknown status"
