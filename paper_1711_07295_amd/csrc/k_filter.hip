@@ -776,11 +776,18 @@ __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, ui
   load_cols<W>(sg_cols, n_cols, j0 + 32, loff, b1);
   for (;;) {
     int phase;  // the ring buffer that holds the columns of step j0
+    // The step's columns for the slow path, copied on the way out of the
+    // loop from the one buffer that holds them: selecting among the three
+    // would read the buffer whose load the step has just issued, and wait
+    // for it (a whole memory round trip per slow-path entry).
+    uint4 cur[W];
     acc[0] = products<W, RT>(b0, rw, 0);
     for (;;) {
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b2);
       if (__builtin_expect(fast_mfma<W, RT, 0>(b0, b1, rw, acc, mx), 0)) {
         phase = 0;
+#pragma unroll
+        for (int kb = 0; kb < W; ++kb) cur[kb] = b0[kb];
         break;
       }
       skip = 0;
@@ -788,6 +795,8 @@ __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, ui
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b0);
       if (__builtin_expect(fast_mfma<W, RT, 1>(b1, b2, rw, acc, mx), 0)) {
         phase = 1;
+#pragma unroll
+        for (int kb = 0; kb < W; ++kb) cur[kb] = b1[kb];
         break;
       }
       skip = 0;
@@ -795,14 +804,13 @@ __device__ __forceinline__ bool sweep_mfma(const uint4 *__restrict__ sg_cols, ui
       load_cols<W>(sg_cols, n_cols, j0 + 64, loff, b1);
       if (__builtin_expect(fast_mfma<W, RT, 2>(b2, b0, rw, acc, mx), 0)) {
         phase = 2;
+#pragma unroll
+        for (int kb = 0; kb < W; ++kb) cur[kb] = b2[kb];
         break;
       }
       skip = 0;
       if ((j0 += 32) >= g1) return true;
     }
-    uint4 cur[W];
-#pragma unroll
-    for (int kb = 0; kb < W; ++kb) cur[kb] = phase == 0 ? b0[kb] : phase == 1 ? b1[kb] : b2[kb];
     if (!emit_mfma<W, RT>(rw, cur, mx, j0, g1, diag, skip, sink)) return false;
     skip = 0;
     if ((j0 += 32) >= g1) return true;

@@ -18,9 +18,10 @@
 // large for that width (its bits saturate) are tested again at the wide
 // width, 4096 bits, when both sets have wide bitmaps.
 //
-// Each wave packs the real entries of its run of the queue (the filter's
-// chunks end in sentinels) so that every lane verifies a survivor; results
-// are appended with one atomic per wave and round (ballot + lane rank).
+// Each wave packs the real entries of its windows of the queue (the
+// filter's chunks end in sentinels) so that every lane verifies a survivor;
+// results are appended with one atomic per wave and round (ballot + lane
+// rank).
 #include "ssj_internal.h"
 
 namespace ssj {
@@ -147,11 +148,12 @@ __device__ __forceinline__ bool verify_entry(uint32_t x, uint32_t y, const Verif
   return hit;
 }
 
-// Each wave verifies a contiguous run of the queue.  The queue holds the
-// filter waves' chunks, whose unused ends are sentinels; the wave reads its
-// run 64 entries at a time and packs the real ones into an LDS list, and
-// verifies them 64 at a time, so that every lane of a verification round
-// has a survivor (the round's length is that of its longest merge).
+// The queue holds the filter waves' chunks, whose unused ends are
+// sentinels.  Wave w reads the queue's 64-entry windows w, w + W, w + 2W, ...
+// (W waves; a run of full chunks is spread over many waves), packs the real
+// entries into an LDS list and verifies them 64 at a time, so that every
+// lane of a verification round has a survivor (the round's length is that
+// of its longest merge).
 __global__ __launch_bounds__(kBlock) void k_verify(
     const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
     const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
@@ -166,8 +168,6 @@ __global__ __launch_bounds__(kBlock) void k_verify(
   const unsigned long long windows = (count + 63) / 64;
   const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
   const unsigned long long wave = (unsigned long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  const unsigned long long per = (windows + n_waves - 1) / n_waves;
-  const unsigned long long w0 = min(wave * per, windows), w1 = min(w0 + per, windows);
   uint32_t fill = 0, surv = 0;
   auto round = [&](uint2 qe, bool ok) {
     unsigned long long key = 0;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(
       }
     }
   };
-  for (unsigned long long w = w0; w < w1; ++w) {
+  for (unsigned long long w = wave; w < windows; w += n_waves) {
     const unsigned long long e = w * 64 + lane;
     uint2 qe = make_uint2(kSentinel, kSentinel);
     if (e < count) qe = queue[e];

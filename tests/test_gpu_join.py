@@ -234,10 +234,13 @@ def test_automatic_width_classes_match_oracle(pq):
     want = oracle.self_join(c.offsets, c.tokens, p, q)
     got, st = ssj.ssj_self_join(_dev(c), p, q, b_bits=0)
     assert np.array_equal(got, want)
-    assert st["b_bits"] == 0 and st["n_classes"] >= 2
+    # a workload this small may take one class: each class costs a launch
+    assert st["b_bits"] == 0 and st["n_classes"] >= 1
     assert st["band_pairs"] == oracle.band_pairs(c.sizes(), p, q)
     bits = st["class_bits"][:st["n_classes"]]
     assert bits == sorted(bits) and set(bits) <= {64, 128, 256, 512}
+    sizes = st["class_max_size"][:st["n_classes"]]
+    assert sizes == sorted(sizes) and sizes[-1] == int(c.sizes().max())
     # the filter's algorithmic work lies between the narrowest and widest class
     assert st["band_pairs"] * (bits[0] // 16 + 1) <= st["filter_ops"]
     assert st["filter_ops"] <= st["band_pairs"] * (bits[-1] // 16 + 1)
@@ -249,23 +252,20 @@ def test_automatic_width_classes_match_oracle(pq):
 
 @pytest.mark.parametrize("flags", [0, ssj.SSJ_FLAG_SURVIVORS_ONLY])
 def test_width_classes_drain_together(flags):
-    """Automatic widths with the smallest queue: the queue fills in the
-    launches of several width classes, each resuming from its own tiles in
-    later rounds.  Pairs and survivor sets equal those of one pass with a
-    large queue, and the pairs equal the oracle's."""
-    c = gen.generate(n_sets=5000, universe=600, zipf_s=1.0, size_dist=gen.SIZE_LOGNORMAL,
-                     size_a=40.0, size_b=1.0, size_lo=1, size_hi=400, planted_frac=0.3,
-                     seed=404)
+    """Automatic widths with a small queue on the 1,000,000-set workload (its
+    width classes: 64 bits for small sets, wider ones for larger): the queue
+    fills in the launches of several classes, each resuming from its own
+    tiles in later rounds.  Pairs and survivor sets equal those of one pass
+    with the library's queue."""
+    c = gen.workload("selfjoin-1m")
     d = _dev(c)
-    one, s1 = ssj.ssj_self_join(d, 1, 3, b_bits=0, flags=flags)
-    got, st = ssj.ssj_self_join(d, 1, 3, b_bits=0, flags=flags, queue_capacity=1)
-    assert st["n_classes"] >= 3
+    one, s1 = ssj.ssj_self_join(d, 4, 5, b_bits=0, flags=flags)
+    got, st = ssj.ssj_self_join(d, 4, 5, b_bits=0, flags=flags, queue_capacity=1 << 14)
+    assert st["n_classes"] >= 2 and s1["n_classes"] == st["n_classes"]
     assert s1["filter_launches"] == s1["n_classes"]
-    assert s1["survivors"] > 3 * 4096 and st["filter_launches"] >= 3 * st["n_classes"]
+    assert s1["survivors"] > 4 * (1 << 14) and st["filter_launches"] >= 3 * st["n_classes"]
     assert st["survivors"] == s1["survivors"] and st["results"] == s1["results"]
     assert np.array_equal(got, one)
-    if not flags:
-        assert np.array_equal(got, oracle.self_join(c.offsets, c.tokens, 1, 3))
 
 
 def test_automatic_width_rejects_caller_bitmaps():
@@ -320,7 +320,9 @@ def test_survivors_automatic_widths_match_oracle(pq):
                      seed=77 + p)
     got, st = ssj.ssj_self_join(_dev(c), p, q, b_bits=0, flags=ssj.SSJ_FLAG_SURVIVORS_ONLY)
     ncls = st["n_classes"]
-    assert ncls >= 3
+    # the classes are the autotuner's (a workload this small may take one);
+    # the brute force below follows whatever widths the call reports
+    assert ncls >= 1
     bounds, widths = st["class_max_size"][:ncls], st["class_bits"][:ncls]
     sizes = c.sizes()
     order = np.lexsort((np.arange(c.n_sets), sizes))     # size order, ties by caller index
@@ -350,3 +352,33 @@ def test_survivors_automatic_widths_match_oracle(pq):
     want = np.array(want, dtype=np.uint32).reshape(-1, 2)
     assert np.array_equal(got, want)
     assert st["survivors"] == len(want)
+
+
+def test_memory_limit_fails_with_nomem_and_no_partial_output():
+    """A cap on the library's working memory below what a call needs: the
+    call fails with SSJ_E_NOMEM, leaves *out = {NULL, 0} (filled with junk
+    before the call), and the library works again once the cap is lifted."""
+    import ctypes
+    c = _ragged(5)
+    d = _dev(c)
+    want = oracle.self_join(c.offsets, c.tokens, 1, 2)
+    lib = ssj.load()
+    cs = d.c()
+    out = ssj.ssj_pairs()
+    out.pairs = ctypes.cast(ctypes.c_void_p(0x1234), ctypes.POINTER(ssj.ssj_pair))
+    out.count = 77
+    try:
+        ssj.ssj_memory_limit(1)
+        st = lib.ssj_self_join(ctypes.byref(cs), None, 64, ssj.SSJ_SIM_JACCARD, 1, 2, None,
+                               ctypes.byref(out), None, ssj._stream(None))
+        assert st == ssj.SSJ_E_NOMEM
+        assert not out.pairs and out.count == 0
+        with pytest.raises(ssj.SsjError) as e:
+            ssj.ssj_self_join(d, 1, 2, b_bits=0)
+        assert e.value.status == ssj.SSJ_E_NOMEM
+    finally:
+        held = ssj.ssj_memory_limit(0)
+    assert held == 0  # the cap freed every idle chunk
+    got, _ = ssj.ssj_self_join(d, 1, 2, b_bits=64)
+    assert np.array_equal(got, want)
+    assert ssj.ssj_memory_limit(0) > 0  # chunks are cached again
