@@ -215,7 +215,8 @@ def main():
     roof = roofline_of(stats, args.steps, args.valu)
     dom = max(range(ncls), key=lambda k: s0["class_ops"][k])
     if (args.workload == "selfjoin-1m" and (args.p, args.q) == (4, 5) and args.bits == 0
-            and args.sim == "jaccard" and s0["class_bits"][dom] == 64 and not args.valu):
+            and args.sim == "jaccard" and s0["class_bits"][dom] == 64 and not args.valu
+            and roof is not None):
         roof["traffic"] = traffic_bytes()
     classes = [{"max_set_size": m, "b_bits": b, "ops": o, "ms": sum(s["class_ms"][k]
                 for s in stats) / args.steps}
@@ -227,7 +228,8 @@ def main():
         "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE_MFMA if roof["bound"] == "mfma" else DTYPE_INT, "data": "synthetic",
+        "dtype": (DTYPE_MFMA if s0["class_bits"][dom] in MFMA_BITS and not args.valu
+                  else DTYPE_INT), "data": "synthetic",
         "config": {"workload": args.workload, "n_sets": col.n_sets,
                    "threshold": f"{args.p}/{args.q}", "similarity": args.sim,
                    "cutoff": args.cutoff, "filter": "valu" if args.valu else "mfma",
@@ -240,6 +242,7 @@ def main():
         "stage_ms": {k: statistics.mean(s[k] for s in stats)
                      for k in ("ms_prepare", "ms_filter", "ms_verify", "ms_emit")},
         "roofline": roof,
+        "parity": golden_parity(args.workload, col.checksum(), args.sim, args.p, args.q, pairs),
         "cpu_baseline": None,
     }
     if graph:
@@ -268,6 +271,29 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def golden_parity(workload, checksum, sim, p, q, pairs):
+    """The timed join's pairs against the oracle's full pair list of the same
+    workload and threshold (SHA-256 of the ascending (i, j) uint32 rows), when
+    tests/golden holds one; None otherwise."""
+    import hashlib
+
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "full_golden.json")
+    if sim != "jaccard" or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        entry = json.load(fh).get(workload)
+    if not entry or entry.get("rows") != "all" or entry.get("checksum") != f"{checksum:#x}":
+        return None
+    want = entry["thresholds"].get(f"{p}/{q}")
+    if want is None:
+        return None
+    got = hashlib.sha256(np.ascontiguousarray(pairs, dtype="<u4").reshape(-1, 2).tobytes())
+    return {"reference": "oracle pair list, tests/golden/full_golden.json",
+            "pairs": int(len(pairs)), "expected_pairs": want["pairs"],
+            "sha256_equal": got.hexdigest() == want["sha256"]}
+
+
 def roofline_of(stats_list, steps, valu=False):
     """Roofline entry of the dominant filter launch (the width class with the
     most algorithmic work), from the library's per-class event timings.
@@ -285,6 +311,11 @@ def roofline_of(stats_list, steps, valu=False):
     launches = sum(s["filter_launches"] for s in stats_list) / steps / ncls
     filt_ms = sum(s["ms_filter"] for s in stats_list) / steps
     band = s0["class_ops"][dom] / (b // 16 + 1)  # band pairs of the class
+    if dom_ms <= 0 or filt_ms <= 0:
+        # a profiler that takes over the completion signals leaves the
+        # library's event pairs without timestamps
+        log("filter event timings read zero: no roofline entry for this run")
+        return None
     stage = {"ops_per_step": s0["filter_ops"], "ms_per_step": filt_ms,
              "valu_equiv_frac": s0["filter_ops"] / (filt_ms / 1e3) / PEAK_INT_OPS}
     if b in MFMA_BITS and not valu and (b < 256 or band >= MFMA_MIN_BAND):

@@ -1,6 +1,6 @@
 /*
  * ssj.h -- exact set similarity join with the Bitmap Filter on one AMD
- * Instinct MI355X (gfx950).  C ABI, version 3.
+ * Instinct MI355X (gfx950).  C ABI, version 4.
  *
  * Method: Sandes, Teodoro, Melo, "Bitmap Filter: Speeding up Exact Set
  * Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
@@ -30,8 +30,10 @@
  *     the default stream).  A join returns after that stream has been
  *     synchronised, because the number of pairs must be known.
  *   - Result pairs are returned in HOST memory owned by the library
- *     (ssj_pairs.pairs), released with ssj_free_pairs.  On any error
- *     *out is {NULL, 0}: there is never a partial result.
+ *     (ssj_pairs.pairs), released with ssj_free_pairs.  Lists of 1 MiB and
+ *     more are page-locked; the library keeps released page-locked buffers
+ *     (up to 1 GiB of them) for later calls.  On any error *out is
+ *     {NULL, 0}: there is never a partial result.
  *   - Calls are re-entrant; calls on distinct streams are independent.
  *     The library takes its working memory per call from a per-device
  *     cache of device memory chunks that it keeps until the process ends.
@@ -46,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SSJ_ABI_VERSION 3
+#define SSJ_ABI_VERSION 4
 
 typedef enum {
   SSJ_OK = 0,
@@ -116,13 +118,18 @@ typedef struct {
   uint64_t results;         /* pairs reported */
   uint64_t filter_ops;      /* algorithmic filter work: per band pair b/16 + 1
                                int32 lane-ops (b/32 xor, b/32 popcount, 1 compare) */
+  uint64_t queue_slots;     /* survivor-queue slots the filter launches reserved,
+                               the sentinel ends of the waves' chunks included
+                               (summed over the rounds) */
   uint32_t filter_launches; /* filter kernel launches (1 + queue drains) */
   uint32_t b_bits;          /* bitmap width asked for (0 = automatic) */
   uint32_t n_classes;       /* row-size classes (1 for a fixed width) */
-  uint32_t class_bits[4];   /* bitmap width of each class */
-  uint32_t class_max_size[4]; /* largest row size of each class */
-  uint64_t class_ops[4];    /* filter_ops of each class */
-  float class_ms[4];        /* filter kernel time of each class (one launch
+  uint32_t class_bits[8];   /* bitmap width of each class */
+  uint32_t class_max_size[8]; /* largest row size of each class */
+  uint64_t class_ops[8];    /* filter_ops of each class */
+  uint64_t class_tiles[8];  /* filter tiles of each class (row tile x column
+                               tile units a wave takes at a time) */
+  float class_ms[8];        /* filter kernel time of each class (one launch
                                per class and queue drain) */
   float ms_total;           /* call entry to pairs in host memory */
   float ms_prepare;         /* validation, size sort, plan, bitmaps */
@@ -223,9 +230,12 @@ int ssj_build_bitmaps_noalloc(const ssj_sets *s, uint32_t b_bits, int method, ui
  *                caller-owned device bitmaps of width b_bits from any
  *                generator (caller order).
  *   b_bits       bitmap width: multiple of 64 in [64, 4096], or 0 for an
- *                automatic width per class of row sizes (64, 128, 256 or
- *                512 bits, wider for larger sets, chosen from the expected
- *                bound of Section 3.4; bitmaps_dev must then be NULL)
+ *                automatic width per class of row sizes (64 to 2048 bits,
+ *                never narrower for larger sets: the widths that minimise
+ *                the expected time of the call's band pairs, from the
+ *                false-survivor odds of the expected bound of Section 3.4
+ *                and costs measured on the GPU; bitmaps_dev must then be
+ *                NULL)
  *   sim          ssj_sim
  *   p, q         threshold t = p / q, 1 <= p <= q (reduced internally);
  *                SSJ_SIM_OVERLAP takes any p >= 1, q >= 1
@@ -287,8 +297,8 @@ typedef struct ssj_index ssj_index;
 /*
  * ssj_index_create -- copy S into the index's own device memory, validate
  * and size-sort it, and build its bitmaps once: Bitmap-Xor at every width
- * the automatic mode may pick (64, 128, 256 and 512 bits) when b_bits is
- * 0, else at b_bits.  The caller may free S afterwards.  The index lives on
+ * the automatic mode may pick (64 to 2048 bits) when b_bits is 0, else at
+ * b_bits.  The caller may free S afterwards.  The index lives on
  * the current device until ssj_index_destroy.
  *   s            the resident collection (device CSR)
  *   b_bits       0 (automatic) or a fixed width, as ssj_self_join
@@ -393,7 +403,8 @@ void ssj_plan_destroy(ssj_plan *plan);
  */
 int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uint32_t *out);
 
-/* Release the pairs of a join.  NULL-safe and idempotent; zeroes *out. */
+/* Release the pairs of a join (any thread).  NULL-safe and idempotent;
+ * zeroes *out. */
 void ssj_free_pairs(ssj_pairs *out);
 
 /* Static text for a status code. */

@@ -10,6 +10,7 @@ Similarity Joins with Bitwise Operations" (arXiv 1711.07295).
 from __future__ import annotations
 
 import ctypes
+import weakref
 import os
 from dataclasses import dataclass
 
@@ -27,6 +28,7 @@ SSJ_FLAG_CUTOFF = 2
 SSJ_FLAG_VALU = 4
 SSJ_FLAG_MFMA = 8
 SSJ_NOALLOC_MAX_SETS = 4_000_000
+ABI_VERSION = 4  # SSJ_ABI_VERSION of include/ssj.h
 
 EXPORTS = ("ssj_build_bitmaps", "ssj_build_bitmaps_noalloc", "ssj_self_join", "ssj_rs_join", "ssj_self_join_batch",
            "ssj_index_create", "ssj_index_query", "ssj_index_destroy", "ssj_cutoff",
@@ -51,10 +53,12 @@ class ssj_pairs(ctypes.Structure):
 class ssj_stats(ctypes.Structure):
     _fields_ = [("band_pairs", ctypes.c_uint64), ("survivors", ctypes.c_uint64),
                 ("results", ctypes.c_uint64), ("filter_ops", ctypes.c_uint64),
+                ("queue_slots", ctypes.c_uint64),
                 ("filter_launches", ctypes.c_uint32), ("b_bits", ctypes.c_uint32),
-                ("n_classes", ctypes.c_uint32), ("class_bits", ctypes.c_uint32 * 4),
-                ("class_max_size", ctypes.c_uint32 * 4), ("class_ops", ctypes.c_uint64 * 4),
-                ("class_ms", ctypes.c_float * 4), ("ms_total", ctypes.c_float),
+                ("n_classes", ctypes.c_uint32), ("class_bits", ctypes.c_uint32 * 8),
+                ("class_max_size", ctypes.c_uint32 * 8), ("class_ops", ctypes.c_uint64 * 8),
+                ("class_tiles", ctypes.c_uint64 * 8),
+                ("class_ms", ctypes.c_float * 8), ("ms_total", ctypes.c_float),
                 ("ms_prepare", ctypes.c_float), ("ms_filter", ctypes.c_float),
                 ("ms_verify", ctypes.c_float), ("ms_emit", ctypes.c_float)]
 
@@ -135,6 +139,9 @@ def load() -> ctypes.CDLL:
         lib.ssj_plan_destroy.restype = None
         lib.ssj_abi_version.argtypes = []
         lib.ssj_abi_version.restype = c_int
+        if lib.ssj_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has C ABI {lib.ssj_abi_version()}, this binding "
+                               f"needs {ABI_VERSION}: rebuild it")
         _lib = lib
     return _lib
 
@@ -189,16 +196,24 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _release(address: int, count: int) -> None:
+    load().ssj_free_pairs(ctypes.byref(ssj_pairs(ctypes.cast(address, ctypes.POINTER(ssj_pair)),
+                                                 count)))
+
+
 def _take(out: ssj_pairs) -> np.ndarray:
+    """The pairs as an (n, 2) uint32 array over the library's own buffer (no
+    copy); the buffer goes back to the library when the array and every view
+    of it are gone."""
     n = int(out.count)
-    try:
-        if n == 0:
-            return np.zeros((0, 2), dtype=np.uint32)
-        raw = np.ctypeslib.as_array(ctypes.cast(out.pairs, ctypes.POINTER(ctypes.c_uint32)),
-                                    shape=(n * 2,))
-        return raw.reshape(n, 2).copy()
-    finally:
+    if n == 0:
         load().ssj_free_pairs(ctypes.byref(out))
+        return np.zeros((0, 2), dtype=np.uint32)
+    address = ctypes.cast(out.pairs, ctypes.c_void_p).value
+    buf = (ctypes.c_uint32 * (2 * n)).from_address(address)
+    done = weakref.finalize(buf, _release, address, n)
+    done.atexit = False  # at exit the process returns the memory
+    return np.frombuffer(buf, dtype=np.uint32).reshape(n, 2)
 
 
 def _opts(queue_capacity=0, tile_cols=0, flags=0):

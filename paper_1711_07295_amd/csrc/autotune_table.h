@@ -2,17 +2,23 @@
 // paper_1711_07295_amd/calibrate.py on subsets of the 1,000,000-set
 // self-join workload at Jaccard 4/5 (fixed widths).
 // Device: AMD Radeon Graphics (gfx950:sramecc+:xnack-, 256 CUs); 2026-12-03.
-// Per width b = 64, 128, 256, 512: filter kernel ns per band pair (sets of
-// 2..40 tokens); ns of a class launch that does not grow with its work (4,000
-// sets); the tile width (columns) with the shortest filter time.  And ns per
-// false survivor (the filter's slow path and queue writes, and its
-// verification; from the sets of 50..89 tokens at b = 64 against b = 128).
+// Per width b = 64 .. 2048: filter kernel ns per band pair (sets of 2..40
+// tokens); ns of a class launch that does not grow with its work (4,000
+// sets); the tile width (columns) with the shortest filter time; the pairs
+// of one step of the width's kernel.  And the ns of a slow-path entry and the
+// ns a survivor adds (queue writes, verification), from the sets of 50..89
+// tokens (64 against 128 bits at 4/5; 64 bits at 1/2); per width, the ns one
+// wave takes to stage a survivor, from one tile where nearly every pair
+// survives (64 x 2048 random sets of b tokens at 1/2).
 #pragma once
 #include <cstdint>
 
 namespace ssj {
-constexpr double kFilterNsPerPair[4] = {3.1104e-05, 4.7709e-05, 1.1181e-04, 8.5296e-04};
-constexpr double kSurvivorNs = 3.7810e+00;
-constexpr double kClassLaunchNs[4] = {3.3195e+04, 3.1676e+04, 4.1395e+04, 3.6435e+04};
-constexpr uint32_t kClassTileCols[4] = {4096, 4096, 4096, 2048};
+constexpr double kFilterNsPerPair[6] = {3.0920e-05, 4.8516e-05, 1.1137e-04, 8.5293e-04, 2.0178e-03, 5.7975e-03};
+constexpr double kSlowEntryNs = 4.4148e+00;
+constexpr double kSurvivorNs = 7.6805e-02;
+constexpr double kSurvivorWaveNs[6] = {4.5511e+00, 4.5986e+00, 4.6424e+00, 5.6521e+00, 6.9843e+00, 1.6969e+01};
+constexpr double kPairsPerStep[6] = {4096.0, 3072.0, 3072.0, 64.0, 64.0, 64.0};
+constexpr double kClassLaunchNs[6] = {3.2556e+04, 3.1516e+04, 4.1235e+04, 3.6036e+04, 4.2674e+04, 7.2831e+04};
+constexpr uint32_t kClassTileCols[6] = {4096, 4096, 4096, 2048, 1024, 2048};
 }  // namespace ssj

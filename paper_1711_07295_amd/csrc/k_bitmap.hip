@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
   // the tokens with t mod b' = k', i.e. bits k' + m b' of b, so word i of b'
   // combines (xor for Bitmap-Xor, or for Bitmap-Set) words i + m (b'/64).
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
+  for (int f = 0; f < 5; ++f) {
     const uint32_t wf = (uint32_t)WO >> (f + 1);
     if (wf == 0 || fold.out[f] == nullptr) continue;
     for (uint32_t i = threadIdx.x; i < ns * wf; i += kBlock) {
@@ -214,6 +214,7 @@ hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint3
                                   out, fold, ctr);
     switch (out_words) {
       SSJ_SEG(1) SSJ_SEG(2) SSJ_SEG(3) SSJ_SEG(4) SSJ_SEG(5) SSJ_SEG(6) SSJ_SEG(7) SSJ_SEG(8)
+      SSJ_SEG(16) SSJ_SEG(32)
       default: break;
     }
 #undef SSJ_SEG
@@ -304,12 +305,13 @@ hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_
   if (n_total == 0) return hipSuccess;
   if (out_words > kMaxWords || out_words < b_bits / 64) return hipErrorInvalidValue;
   if (perm && !side_of) return hipErrorInvalidValue;
-  FoldOut fold{{nullptr, nullptr, nullptr}};
+  FoldOut fold{};
   if (fold_in) {
     // folding needs a power-of-two width built at exactly its words, by the
-    // segmented kernel (Xor or Set, at most 8 words)
+    // segmented kernel (Xor or Set, at most kMaxFoldWords words)
     const bool pow2w = (out_words & (out_words - 1)) == 0 && b_bits == 64 * out_words;
-    if (!pow2w || method == SSJ_BM_NEXT || out_words > 8 || !(rank || !perm) || !seg_blocks)
+    if (!pow2w || method == SSJ_BM_NEXT || out_words > kMaxFoldWords || !(rank || !perm) ||
+        !seg_blocks)
       return hipErrorInvalidValue;
     fold = *fold_in;
   }

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *__restrict__ p, u
 __global__ void k_reset_round(JoinCounters *ctr) {
   if (threadIdx.x == 0) {
     ctr->queue_count = 0;
+    ctr->long_count = 0;
     ctr->overflow = 0;
     ctr->n_resume = 0;
   }

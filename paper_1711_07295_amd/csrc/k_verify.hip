@@ -22,6 +22,8 @@
 // filter's chunks end in sentinels) so that every lane verifies a survivor;
 // results are appended with one atomic per wave and round (ballot + lane
 // rank).
+#include <atomic>
+
 #include "ssj_internal.h"
 
 namespace ssj {
@@ -41,7 +43,8 @@ __host__ __device__ __forceinline__ void load_window(const uint32_t *__restrict_
 // merge: count the common tokens of the current windows, then drop the
 // window whose last token is smaller (both when equal).  A common token sits
 // in both current windows at some step and leaves with the dropped window,
-// so it is counted once.  Stops as soon as the tokens left cannot reach need.
+// so it is counted once.  Stops as soon as the count reaches need, or the
+// tokens left cannot reach it.
 __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restrict__ rp, uint32_t a,
                                                 const uint32_t *__restrict__ sp, uint32_t c,
                                                 uint32_t need) {
@@ -50,6 +53,7 @@ __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restr
   load_window(rp, a, 0, rw);
   load_window(sp, c, 0, sw);
   while (ia < a && ic < c) {
+    if (o >= need) return true;
     if (o + min(a - ia, c - ic) < need) return false;
     const uint32_t nr = min(a - ia, (uint32_t)kWin), ns = min(c - ic, (uint32_t)kWin);
 #pragma unroll
@@ -76,75 +80,224 @@ __host__ __device__ __forceinline__ bool overlap_reaches(const uint32_t *__restr
   return o >= need;
 }
 
-// Hamming distance of two bitmaps of w 64-bit words, two words per
-// 16-byte load (both bitmaps start on a 16-byte boundary when w is even).
-__device__ __forceinline__ uint32_t distance(const uint64_t *__restrict__ x,
-                                             const uint64_t *__restrict__ y, uint32_t w) {
-  uint32_t h = 0;
-  if ((w & 1u) == 0) {
-    const uint4 *a = reinterpret_cast<const uint4 *>(x), *b = reinterpret_cast<const uint4 *>(y);
-    for (uint32_t k = 0; k < w / 2; ++k) {
-      const uint4 p = a[k], q = b[k];
-      h += (uint32_t)__popc(p.x ^ q.x) + (uint32_t)__popc(p.y ^ q.y) +
-           (uint32_t)__popc(p.z ^ q.z) + (uint32_t)__popc(p.w ^ q.w);
-    }
-  } else {
-    for (uint32_t k = 0; k < w; ++k) h += (uint32_t)__popcll(x[k] ^ y[k]);
+// |r n s| with the whole wave, for one pair of long sets (the same on every
+// lane).  Lane l takes r's tokens [a l / 64, a (l + 1) / 64) and counts
+// those that s holds.  s is cut by 64 splitters s[c j / 64], one load per
+// lane; a lane finds the last splitter not above its first token by a
+// binary search over the lanes' splitters (six shuffles) and merges its
+// tokens with s from there.  Tokens of s before that splitter are smaller
+// than every token of the lane's, so each token of r is counted exactly
+// when s holds it.  About four memory round trips, against one per eight
+// tokens for a lane's own merge.
+__device__ __forceinline__ uint32_t wave_overlap(const uint32_t *__restrict__ rp, uint32_t a,
+                                                 const uint32_t *__restrict__ sp, uint32_t c) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lo = (uint32_t)(((uint64_t)a * lane) >> 6);
+  const uint32_t hi = (uint32_t)(((uint64_t)a * (lane + 1)) >> 6);
+  const uint32_t sj = (uint32_t)(((uint64_t)c * lane) >> 6);  // < c
+  const uint32_t sv = sp[sj];
+  const bool has = lo < hi;
+  const uint32_t first = has ? rp[lo] : 0u;
+  int j = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1) {
+    const uint32_t cand = (uint32_t)__shfl((int)sv, j + step, 64);
+    if (cand <= first) j += step;
   }
+  const uint32_t from = (uint32_t)(((uint64_t)c * (uint32_t)j) >> 6);
+  uint32_t o = 0;
+  if (has) {
+    const uint32_t na = hi - lo, nc = c - from;
+    const uint32_t *__restrict__ r = rp + lo, *__restrict__ t = sp + from;
+    uint32_t ia = 0, ic = 0;
+    uint32_t rw[kWin], sw[kWin];
+    load_window(r, na, 0, rw);
+    load_window(t, nc, 0, sw);
+    while (ia < na && ic < nc) {
+      const uint32_t nr = min(na - ia, (uint32_t)kWin), ns = min(nc - ic, (uint32_t)kWin);
+#pragma unroll
+      for (int x = 0; x < kWin; ++x)
+#pragma unroll
+        for (int y = 0; y < kWin; ++y)
+          o += ((uint32_t)x < nr && (uint32_t)y < ns && rw[x] == sw[y]) ? 1u : 0u;
+      uint32_t rmax = rw[0], smax = sw[0];
+#pragma unroll
+      for (int k = 1; k < kWin; ++k) {
+        if ((uint32_t)k < nr) rmax = rw[k];
+        if ((uint32_t)k < ns) smax = sw[k];
+      }
+      if (rmax <= smax) {
+        ia += nr;
+        load_window(r, na, ia, rw);
+      }
+      if (smax <= rmax) {
+        ic += ns;
+        load_window(t, nc, ic, sw);
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) o += (uint32_t)__shfl_xor((int)o, d, 64);
+  return o;
+}
+
+// Hamming distance of two bitmaps of W 64-bit words (W even: both start on
+// a 16-byte boundary), every load issued before the first popcount so that
+// the test costs one round trip.
+template <int W>
+__device__ __forceinline__ uint32_t distance(const uint64_t *__restrict__ x,
+                                             const uint64_t *__restrict__ y) {
+  static_assert(W % 2 == 0, "pairs of words per 16-byte load");
+  const uint4 *a = reinterpret_cast<const uint4 *>(x), *b = reinterpret_cast<const uint4 *>(y);
+  uint4 p[W / 2], q[W / 2];
+#pragma unroll
+  for (int k = 0; k < W / 2; ++k) {
+    p[k] = a[k];
+    q[k] = b[k];
+  }
+  uint32_t h = 0;
+#pragma unroll
+  for (int k = 0; k < W / 2; ++k)
+    h += (uint32_t)__popc(p[k].x ^ q[k].x) + (uint32_t)__popc(p[k].y ^ q[k].y) +
+         (uint32_t)__popc(p[k].z ^ q[k].z) + (uint32_t)__popc(p[k].w ^ q[k].w);
   return h;
 }
 
+// The wide test's distance, kWideWords words in batches of 8.
+__device__ __forceinline__ uint32_t wide_distance(const uint64_t *__restrict__ x,
+                                                  const uint64_t *__restrict__ y) {
+  uint32_t h = 0;
+#pragma unroll 1
+  for (uint32_t k = 0; k < kWideWords; k += 8) h += distance<8>(x + k, y + k);
+  return h;
+}
+
+// Pairs whose sizes sum to more than kLongMerge, and that pass the cascade
+// test, are merged by a whole wave (wave_overlap) in a second launch: a
+// lane's own merge takes a memory round trip per eight tokens, and one long
+// true pair would hold its whole round that long.
+constexpr uint32_t kLongMerge = 128;
+
+struct VerifyArgs {
+  VerifySpace rows, cols;
+  const uint32_t *side_task;
+  const TaskDesc *tasks;
+  const uint32_t *tables;
+  int ib, jb;
+  uint32_t survivors_only;
+  uint2 *longq;  // the deferred long pairs (capacity: the queue's), or NULL
+};
+
+// What verify_entry reads of a call's one task (ONE): its descriptor, the
+// CSR of its row and column sides and their wide ranges, read once per
+// wave.
+struct OneTask {
+  TaskDesc td;
+  const uint64_t *r_off, *c_off;
+  const uint32_t *r_tok, *c_tok;
+  uint32_t r_wlo, c_wlo, r_wslot, c_wslot;
+};
+
+__device__ __forceinline__ OneTask one_task(const VerifyArgs &va) {
+  OneTask one{};
+  one.td = va.tasks[0];
+  const SideDesc &dr = va.rows.sides[one.td.row_side], &dc = va.cols.sides[one.td.col_side];
+  one.r_off = dr.offsets;
+  one.r_tok = dr.tokens;
+  one.c_off = dc.offsets;
+  one.c_tok = dc.tokens;
+  if (va.rows.bmw) {
+    one.r_wlo = va.rows.wide_lo[one.td.row_side];
+    one.c_wlo = va.cols.wide_lo[one.td.col_side];
+    one.r_wslot = va.rows.wide_slot[one.td.row_side];
+    one.c_wslot = va.cols.wide_slot[one.td.col_side];
+  }
+  return one;
+}
+
 // Verify one survivor (row x, column y of the two spaces): its result key,
-// or false.  Sizes, the task's least overlap and the cascade bitmaps come
-// from arrays indexed by the queue entry itself, so the false survivors
-// that the wider bitmaps reject (most of them) never touch the caller's
-// offsets or tokens.
-__device__ __forceinline__ bool verify_entry(uint32_t x, uint32_t y, const VerifySpace &rows,
-                                             const VerifySpace &cols,
-                                             const uint32_t *__restrict__ side_task,
-                                             const TaskDesc *__restrict__ tasks,
-                                             const uint32_t *__restrict__ tables, int ib, int jb,
-                                             uint32_t survivors_only, uint32_t w2,
+// or false.  Sizes, the task's least overlap and the cascade bitmaps (W2
+// words per set, 0: no cascade) come from arrays indexed by the queue entry
+// itself, so the false survivors that the wider bitmaps reject (most of
+// them) never touch the caller's offsets or tokens.  Every load that needs
+// only (x, y) -- sides, positions, sizes, cascade bitmaps -- is issued
+// first, so that a survivor's chain of dependent round trips before its
+// merge is short.  ONE: the call has one task, whose descriptor, sides and
+// wide ranges are uniform and come from `one`.
+// Result key of a qualifying pair: (task, caller i, caller j), (min, max)
+// for a self-join task.
+__device__ __forceinline__ unsigned long long result_key(uint32_t px, uint32_t py,
+                                                         const TaskDesc &td, uint32_t task,
+                                                         int ib, int jb) {
+  uint32_t ki = px, kj = py;
+  if (td.self && kj < ki) {
+    const uint32_t t = ki;
+    ki = kj;
+    kj = t;
+  }
+  unsigned long long key = ((unsigned long long)ki << jb) | kj;
+  if (ib + jb < 64) key |= (unsigned long long)task << (ib + jb);
+  return key;
+}
+
+template <int W2, bool ONE>
+__device__ __forceinline__ bool verify_entry(uint32_t x, uint32_t y, const VerifyArgs &va,
+                                             const OneTask &one, bool &defer,
                                              unsigned long long &key) {
-  const uint32_t sr = rows.side_of[x], sc = cols.side_of[y];
+  const VerifySpace &rows = va.rows, &cols = va.cols;
+  const uint32_t sr = ONE ? 0u : rows.side_of[x], sc = ONE ? 0u : cols.side_of[y];
+  const uint32_t px = rows.perm[x], py = cols.perm[y];
   const uint32_t a = rows.sizes[x], c = cols.sizes[y];
-  const uint32_t task = side_task[sr];
-  const TaskDesc &td = tasks[task];
+  uint32_t h2 = 0;
+  if (W2) h2 = distance<W2 ? W2 : 2>(rows.bm2 + (size_t)x * W2, cols.bm2 + (size_t)y * W2);
+  const uint32_t task = ONE ? 0u : va.side_task[sr];
+  const TaskDesc td = ONE ? one.td : va.tasks[task];
+  // with one task the CSR offsets come with the least overlap (a few bytes
+  // per survivor); otherwise only pairs that pass the bitmap tests read them
+  uint64_t r0 = 0, s0 = 0;
+  if (ONE) {
+    r0 = one.r_off[px];
+    s0 = one.c_off[py];
+  }
   bool hit = true;
-  if (!survivors_only) {
-    const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
-                                                   : tables[td.omin_off + a + c];
+  if (!va.survivors_only) {
+    // the table entry is read for every function (Cosine's one unused
+    // entry for Cosine) so that its load is not held back by the branch
+    const bool cosine = td.sim == SSJ_SIM_COSINE;
+    const uint32_t t_need = va.tables[td.omin_off + (cosine ? 0u : a + c)];
+    const uint32_t need = cosine ? cosine_omin(a, c, td.p, td.q) : t_need;
     const int64_t slack = (int64_t)a + c - 2 * (int64_t)need;
     // second bitmap test at the cascade width (Theorem 1 holds at every
     // width): most false survivors of a narrow class end here
-    hit = a != 0 && c != 0 && slack >= 0;
-    if (hit && rows.bm2)
-      hit = (int64_t)distance(rows.bm2 + (size_t)x * w2, cols.bm2 + (size_t)y * w2, w2) <= slack;
+    hit = a != 0 && c != 0 && slack >= 0 && (int64_t)h2 <= slack;
     // and at the wide width when both sets have wide bitmaps (sets too
     // large for the cascade width, whose bits saturate)
     if (hit && rows.bmw) {
-      const uint32_t lr = rows.wide_lo[sr], lc = cols.wide_lo[sc];
-      if (x >= lr && y >= lc)
-        hit = (int64_t)distance(rows.bmw + (size_t)(rows.wide_slot[sr] + (x - lr)) * kWideWords,
-                                cols.bmw + (size_t)(cols.wide_slot[sc] + (y - lc)) * kWideWords,
-                                kWideWords) <= slack;
+      const uint32_t lr = ONE ? one.r_wlo : rows.wide_lo[sr];
+      const uint32_t lc = ONE ? one.c_wlo : cols.wide_lo[sc];
+      if (x >= lr && y >= lc) {
+        const uint32_t wr = ONE ? one.r_wslot : rows.wide_slot[sr];
+        const uint32_t wc = ONE ? one.c_wslot : cols.wide_slot[sc];
+        hit = (int64_t)wide_distance(rows.bmw + (size_t)(wr + (x - lr)) * kWideWords,
+                                     cols.bmw + (size_t)(wc + (y - lc)) * kWideWords) <= slack;
+      }
+    }
+    // pairs of long sets go to the wave-cooperative merge
+    if (hit && va.longq && a + c > kLongMerge) {
+      defer = true;
+      return false;
     }
     if (hit) {
-      const SideDesc &dr = rows.sides[sr], &dc = cols.sides[sc];
-      const uint64_t r0 = dr.offsets[rows.perm[x]], s0 = dc.offsets[cols.perm[y]];
-      hit = overlap_reaches(dr.tokens + r0, a, dc.tokens + s0, c, need);
+      if (!ONE) {
+        r0 = rows.sides[sr].offsets[px];
+        s0 = cols.sides[sc].offsets[py];
+      }
+      const uint32_t *rt = ONE ? one.r_tok : rows.sides[sr].tokens;
+      const uint32_t *ct = ONE ? one.c_tok : cols.sides[sc].tokens;
+      hit = overlap_reaches(rt + r0, a, ct + s0, c, need);
     }
   }
-  if (hit) {
-    uint32_t ki = rows.perm[x], kj = cols.perm[y];
-    if (td.self && kj < ki) {
-      const uint32_t t = ki;
-      ki = kj;
-      kj = t;
-    }
-    key = ((unsigned long long)ki << jb) | kj;
-    if (ib + jb < 64) key |= (unsigned long long)task << (ib + jb);
-  }
+  if (hit) key = result_key(px, py, td, task, va.ib, va.jb);
   return hit;
 }
 
@@ -154,12 +307,12 @@ __device__ __forceinline__ bool verify_entry(uint32_t x, uint32_t y, const Verif
 // entries into an LDS list and verifies them 64 at a time, so that every
 // lane of a verification round has a survivor (the round's length is that
 // of its longest merge).
-__global__ __launch_bounds__(kBlock) void k_verify(
-    const uint2 *__restrict__ queue, unsigned long long cap, VerifySpace rows, VerifySpace cols,
-    const uint32_t *__restrict__ side_task, const TaskDesc *__restrict__ tasks,
-    const uint32_t *__restrict__ tables, int ib, int jb, uint32_t survivors_only, uint32_t w2,
-    unsigned long long *__restrict__ results, unsigned long long results_cap,
-    JoinCounters *__restrict__ ctr) {
+template <int W2, bool ONE>
+__global__ __launch_bounds__(kBlock) void k_verify(const uint2 *__restrict__ queue,
+                                                   unsigned long long cap, VerifyArgs va,
+                                                   unsigned long long *__restrict__ results,
+                                                   unsigned long long results_cap,
+                                                   JoinCounters *__restrict__ ctr) {
   __shared__ uint2 pend[kBlock / 64][128];
   uint2 *buf = pend[threadIdx.x >> 6];
   const uint32_t lane = threadIdx.x & 63;
@@ -169,10 +322,21 @@ __global__ __launch_bounds__(kBlock) void k_verify(
   const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
   const unsigned long long wave = (unsigned long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   uint32_t fill = 0, surv = 0;
+  const OneTask one = ONE ? one_task(va) : OneTask{};
   auto round = [&](uint2 qe, bool ok) {
     unsigned long long key = 0;
-    const bool hit = ok && verify_entry(qe.x, qe.y, rows, cols, side_task, tasks, tables, ib, jb,
-                                        survivors_only, w2, key);
+    bool defer = false;
+    const bool hit = ok && verify_entry<W2, ONE>(qe.x, qe.y, va, one, defer, key);
+    const unsigned long long dm = __ballot(defer);
+    if (dm) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&ctr->long_count, (unsigned long long)__popcll(dm));
+      base = __shfl(base, 0, 64);
+      if (defer) {
+        const unsigned long long pos = base + (unsigned long long)__popcll(dm & __lanemask_lt());
+        if (pos < cap) va.longq[pos] = qe;
+      }
+    }
     const unsigned long long m = __ballot(hit);
     if (m) {
       unsigned long long base = 0;
@@ -184,11 +348,16 @@ __global__ __launch_bounds__(kBlock) void k_verify(
       }
     }
   };
-  for (unsigned long long w = wave; w < windows; w += n_waves) {
+  // the next window's entry is loaded before the current one is used
+  auto entry = [&](unsigned long long w) {
     const unsigned long long e = w * 64 + lane;
-    uint2 qe = make_uint2(kSentinel, kSentinel);
-    if (e < count) qe = queue[e];
-    const bool valid = qe.x < rows.n && qe.y < cols.n;
+    return w < windows && e < count ? queue[e] : make_uint2(kSentinel, kSentinel);
+  };
+  uint2 next = entry(wave);
+  for (unsigned long long w = wave; w < windows; w += n_waves) {
+    const uint2 qe = next;
+    next = entry(w + n_waves);
+    const bool valid = qe.x < va.rows.n && qe.y < va.cols.n;
     const unsigned long long m = __ballot(valid);
     if (valid) buf[fill + (uint32_t)__popcll(m & __lanemask_lt())] = qe;
     fill += (uint32_t)__popcll(m);  // < 128: at most 63 were left over
@@ -209,10 +378,53 @@ __global__ __launch_bounds__(kBlock) void k_verify(
     surv += lane < fill ? 1u : 0u;
     round(mine, lane < fill);
   }
-  // survivors seen, one atomic per wave
+  // survivors seen, one atomic per workgroup (same-address atomics from
+  // every XCD are served one at a time)
+  __shared__ uint32_t block_surv;
+  if (threadIdx.x == 0) block_surv = 0;
+  __syncthreads();
   uint32_t s = surv;
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-  if (lane == 0 && s) atomicAdd(&ctr->survivors, (unsigned long long)s);
+  if (lane == 0 && s) atomicAdd(&block_surv, s);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_surv) atomicAdd(&ctr->survivors, (unsigned long long)block_surv);
+}
+
+// The deferred long pairs (their bitmap tests passed): one wave per pair,
+// the pairs dealt to the waves in turn.
+template <bool ONE>
+__global__ __launch_bounds__(kBlock) void k_verify_long(unsigned long long cap, VerifyArgs va,
+                                                        unsigned long long *__restrict__ results,
+                                                        unsigned long long results_cap,
+                                                        JoinCounters *__restrict__ ctr) {
+  const uint32_t lane = threadIdx.x & 63;
+  unsigned long long count = ctr->long_count;
+  if (count > cap) count = cap;
+  const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
+  const unsigned long long wave = (unsigned long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const OneTask one = ONE ? one_task(va) : OneTask{};
+  const VerifySpace &rows = va.rows, &cols = va.cols;
+  for (unsigned long long e = wave; e < count; e += n_waves) {
+    const uint2 qe = va.longq[e];
+    const uint32_t x = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
+    const uint32_t y = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
+    const uint32_t sr = ONE ? 0u : rows.side_of[x], sc = ONE ? 0u : cols.side_of[y];
+    const uint32_t px = rows.perm[x], py = cols.perm[y];
+    const uint32_t a = rows.sizes[x], c = cols.sizes[y];
+    const uint32_t task = ONE ? 0u : va.side_task[sr];
+    const TaskDesc td = ONE ? one.td : va.tasks[task];
+    const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
+                                                   : va.tables[td.omin_off + a + c];
+    const uint64_t r0 = ONE ? one.r_off[px] : rows.sides[sr].offsets[px];
+    const uint64_t s0 = ONE ? one.c_off[py] : cols.sides[sc].offsets[py];
+    const uint32_t *rt = ONE ? one.r_tok : rows.sides[sr].tokens;
+    const uint32_t *ct = ONE ? one.c_tok : cols.sides[sc].tokens;
+    const uint32_t o = wave_overlap(rt + r0, a, ct + s0, c);
+    if (o >= need && lane == 0) {
+      const unsigned long long pos = atomicAdd(&ctr->results, 1ull);
+      if (pos < results_cap) results[pos] = result_key(px, py, td, task, va.ib, va.jb);
+    }
+  }
 }
 
 // Sorted keys -> pairs, and the first result of every task: the key at x
@@ -240,34 +452,93 @@ __global__ __launch_bounds__(kBlock) void k_split_results(
 
 }  // namespace
 
-// Blocks of k_verify resident at once on the current device.  The grid
-// strides over the queue with a fixed share per lane: blocks beyond what
-// the compute units hold would start only when the first ones end, and the
-// launch would take two rounds of its latency-bound loop instead of one.
+// Blocks of a k_verify instance resident at once on the current device
+// (queried once per instance and device).  The grid strides over the queue
+// with a fixed share per lane: blocks beyond what the compute units hold
+// would start only when the first ones end, and the launch would take two
+// rounds of its latency-bound loop instead of one.
+constexpr int kVerifyDevices = 64;
+
+template <int W2, bool ONE>
 static int verify_grid_blocks() {
+  static std::atomic<int> cached[kVerifyDevices];
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (dev >= 0 && dev < kVerifyDevices) {
+    const int c = cached[dev].load(std::memory_order_relaxed);
+    if (c) return c;
+  }
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_verify, kBlock, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_verify<W2, ONE>, kBlock, 0) !=
+          hipSuccess ||
       per_cu <= 0)
     per_cu = 4;
+  if (dev >= 0 && dev < kVerifyDevices) cached[dev].store(cus * per_cu, std::memory_order_relaxed);
   return cus * per_cu;
 }
 
-hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
-                         VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
-                         const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         uint32_t w2, unsigned long long *results,
-                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st) {
+template <bool ONE>
+static int verify_long_grid_blocks() {
+  static std::atomic<int> cached[kVerifyDevices];
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (dev >= 0 && dev < kVerifyDevices) {
+    const int c = cached[dev].load(std::memory_order_relaxed);
+    if (c) return c;
+  }
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_verify_long<ONE>, kBlock, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  if (dev >= 0 && dev < kVerifyDevices) cached[dev].store(cus * per_cu, std::memory_order_relaxed);
+  return cus * per_cu;
+}
+
+template <int W2, bool ONE>
+static void launch_verify_as(const uint2 *queue, unsigned long long cap, const VerifyArgs &va,
+                             unsigned long long *results, unsigned long long results_cap,
+                             JoinCounters *ctr, hipStream_t st) {
+  hipLaunchKernelGGL((k_verify<W2, ONE>), dim3(verify_grid_blocks<W2, ONE>()), dim3(kBlock), 0,
+                     st, queue, cap, va, results, results_cap, ctr);
+  if (va.longq)
+    hipLaunchKernelGGL((k_verify_long<ONE>), dim3(verify_long_grid_blocks<ONE>()), dim3(kBlock),
+                       0, st, cap, va, results, results_cap, ctr);
+}
+
+hipError_t launch_verify(const uint2 *queue, uint2 *longq, unsigned long long cap,
+                         VerifySpace rows, VerifySpace cols, const uint32_t *side_task,
+                         const TaskDesc *tasks, uint32_t n_tasks, const uint32_t *tables, int ib,
+                         int jb, uint32_t survivors_only, uint32_t w2,
+                         unsigned long long *results, unsigned long long results_cap,
+                         JoinCounters *ctr, hipStream_t st) {
   if ((rows.bm2 == nullptr) != (cols.bm2 == nullptr) || (rows.bm2 && !w2))
     return hipErrorInvalidValue;
   if ((rows.bmw == nullptr) != (cols.bmw == nullptr)) return hipErrorInvalidValue;
-  dim3 grid(verify_grid_blocks());
-  hipLaunchKernelGGL(k_verify, grid, dim3(kBlock), 0, st, queue, cap, rows, cols, side_task,
-                     tasks, tables, ib, jb, survivors_only, w2, results, results_cap,
-                     ctr);
+  if (!rows.bm2) w2 = 0;
+  if (w2 != 0 && w2 != 2 && w2 != 4 && w2 != 8) return hipErrorInvalidValue;
+  if (n_tasks == 0) return hipErrorInvalidValue;
+  // only pairs that passed a cascade test are deferred: they are nearly all
+  // true pairs, which a lane's merge cannot leave early; without a cascade
+  // most survivors are false, and a lane's merge rejects them in a few
+  // windows
+  const VerifyArgs va{rows, cols, side_task, tasks, tables, ib, jb, survivors_only,
+                      survivors_only || !rows.bm2 ? nullptr : longq};
+  const bool one = n_tasks == 1;
+  switch (w2 * 2 + (one ? 1 : 0)) {
+    case 0: launch_verify_as<0, false>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 1: launch_verify_as<0, true>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 4: launch_verify_as<2, false>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 5: launch_verify_as<2, true>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 8: launch_verify_as<4, false>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 9: launch_verify_as<4, true>(queue, cap, va, results, results_cap, ctr, st); break;
+    case 16: launch_verify_as<8, false>(queue, cap, va, results, results_cap, ctr, st); break;
+    default: launch_verify_as<8, true>(queue, cap, va, results, results_cap, ctr, st); break;
+  }
   return hipGetLastError();
 }
 

@@ -70,6 +70,67 @@ inline void check(hipError_t e) {
   throw Fail{SSJ_E_DEVICE};
 }
 
+// Host buffers of result pair lists.  A list of at least kPinnedMin bytes
+// goes to page-locked memory, so that its copy from the device runs at the
+// link's rate and touches no fresh pages; ssj_free_pairs keeps such buffers
+// for later calls (at most kPinnedIdleMax bytes of them idle).  Smaller
+// lists, and any a page-locked allocation fails for, use malloc.
+class HostPairs {
+ public:
+  static HostPairs &get() {
+    static HostPairs *h = new HostPairs;  // never destroyed: buffers may outlive exit handlers
+    return *h;
+  }
+  ssj_pair *alloc(uint64_t n) {
+    const size_t bytes = (size_t)n * sizeof(ssj_pair);
+    if (bytes >= kPinnedMin) {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = idle_.lower_bound(bytes);
+      if (it != idle_.end() && it->first <= 2 * bytes) {
+        void *p = it->second;
+        idle_bytes_ -= it->first;
+        idle_.erase(it);
+        return static_cast<ssj_pair *>(p);
+      }
+      size_t cap = kPinnedMin;
+      while (cap < bytes) cap *= 2;
+      void *p = nullptr;
+      if (hipHostMalloc(&p, cap, hipHostMallocDefault) == hipSuccess && p) {
+        cap_[p] = cap;
+        return static_cast<ssj_pair *>(p);
+      }
+      (void)hipGetLastError();
+    }
+    return static_cast<ssj_pair *>(std::malloc(bytes));
+  }
+  void release(void *p) {
+    if (!p) return;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = cap_.find(p);
+      if (it != cap_.end()) {
+        const size_t cap = it->second;
+        if (idle_bytes_ + cap <= kPinnedIdleMax) {
+          idle_.emplace(cap, p);
+          idle_bytes_ += cap;
+        } else {
+          cap_.erase(it);
+          (void)hipHostFree(p);
+        }
+        return;
+      }
+    }
+    std::free(p);
+  }
+
+ private:
+  static constexpr size_t kPinnedMin = size_t(1) << 20, kPinnedIdleMax = size_t(1) << 30;
+  std::mutex mu_;
+  std::multimap<size_t, void *> idle_;  // capacity -> idle buffer
+  std::map<void *, size_t> cap_;        // every page-locked buffer -> capacity
+  size_t idle_bytes_ = 0;
+};
+
 // Device memory chunks kept between calls, per device.  A call takes chunks
 // at its start and gives them back only after its final stream
 // synchronisation, so a chunk is never in use by two calls.  Chunk sizes are
@@ -298,10 +359,10 @@ struct Space {
   JoinCounters ctr_h{};
   // bitmaps in size order, one array per width
   uint32_t n_bm = 0;
-  uint32_t bm_words[kMaxClasses] = {0, 0, 0, 0};
-  uint64_t *bm[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  uint32_t bm_words[kMaxClasses] = {};
+  uint64_t *bm[kMaxClasses] = {};
   // sign planes of the bitmaps (matrix-core filter), beside bm[k]
-  uint4 *sg[kMaxClasses] = {nullptr, nullptr, nullptr, nullptr};
+  uint4 *sg[kMaxClasses] = {};
   // wide bitmaps of the sets larger than kWideMin (verification)
   bool wide_built = false;
   uint64_t *bmw = nullptr;
@@ -477,28 +538,32 @@ void space_wide(Space &sp, Arena &ar, hipStream_t st, Launcher *L = nullptr) {
   });
 }
 
-// Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to 8
-// words come from one pass over the tokens: the widest is built and the
-// narrower ones are folded from it in the same kernel.
+// Bitmap-Xor bitmaps at several widths.  Power-of-two widths of up to
+// kMaxFoldWords words come from one pass over the tokens: the widest is
+// built and the narrower ones are folded from it in the same kernel.
 void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits, uint32_t n,
                          Arena &ar, JoinCounters *ctr, hipStream_t st, Launcher *L = nullptr) {
   uint32_t need_w[kMaxClasses + 1], need_b[kMaxClasses + 1], m = 0, wmax = 0;
-  bool foldable = sp.rank != nullptr;
   for (uint32_t k = 0; k < n; ++k) {
     if (sp.bitmaps(words[k])) continue;
+    const bool fold = sp.rank != nullptr && (words[k] & (words[k] - 1)) == 0 &&
+                      words[k] <= kMaxFoldWords && bits[k] == 64 * words[k];
+    if (!fold) {
+      // wider than a fold allows: a pass of its own
+      space_bitmaps(sp, words[k], bits[k], ar, ctr, st, L);
+      continue;
+    }
     need_w[m] = words[k];
     need_b[m] = bits[k];
-    foldable = foldable && (words[k] & (words[k] - 1)) == 0 && words[k] <= 8 &&
-               bits[k] == 64 * words[k];
     wmax = std::max(wmax, words[k]);
     ++m;
   }
   if (m == 0) return;
-  if (!foldable || m == 1 || sp.n_bm + m > kMaxClasses) {
+  if (m == 1 || sp.n_bm + m > kMaxClasses) {
     for (uint32_t k = 0; k < m; ++k) space_bitmaps(sp, need_w[k], need_b[k], ar, ctr, st, L);
     return;
   }
-  FoldOut fold{{nullptr, nullptr, nullptr}};
+  FoldOut fold{};
   uint64_t *widest = ar.alloc<uint64_t>(sp.n * wmax);
   for (uint32_t k = 0; k < m; ++k) {
     uint64_t *dst = widest;
@@ -616,17 +681,31 @@ double binomial_cdf(int n, double pi, int64_t k) {
 // unrelated sets differ as Binomial(b, pi) with pi = (1 - (1 - 2/b)^L) / 2,
 // the chance that a bit receives an odd number of the L tokens (the quantity
 // Eq. 5 sums; Section 3.4).  A pair is a false survivor when that count is at
-// most slack(L).  With the costs measured on the GPU (calibrate.py writes
-// them to autotune_table.h) -- the filter's time per band pair at each width,
-// the time a survivor costs (the filter's slow path and queue writes, and its
-// verification), and the fixed cost of a width class's launch -- the widths
-// b(a), b in {64, 128, 256, 512} and never decreasing with the size, are the
-// ones that minimise the task's expected time
-//   sum over row sizes a of  band(a) * (filter(b(a)) + P(false survivor) * survivor(b(a)))
-//   + the launch cost of every width used,
-// band(a) being the task's band pairs of rows of size a.  A dynamic program
-// over the sizes finds them.
-constexpr uint32_t kAutoWords[4] = {1, 2, 4, 8};  // b = 64, 128, 256, 512
+// most slack(L), with probability P.  The filter leaves its fast path for a
+// step of s pairs (kPairsPerStep of the width's kernel) that keeps any pair,
+// with probability 1 - (1 - P)^s, and every survivor costs queue writes and
+// a verification.  So a band pair at width b is expected to cost
+//   filter(b) + (1 - (1 - P)^s) * entry / s + P * survivor,
+// with the costs measured on the GPU (calibrate.py writes them to
+// autotune_table.h): the filter's time per band pair at each width, the time
+// of a slow-path entry, the time a survivor adds, and the fixed cost of a
+// width class's launch.  The survivor's time is a throughput figure, right
+// when the survivors spread over the whole grid; the survivors of a size
+// whose rows fill few tiles are staged by the few waves that own those
+// tiles, one after the other, and the class waits for them.  So a survivor
+// costs at least the time one wave takes to stage it at that width (measured
+// too) divided by the tiles of its size (row tiles times column tiles of the
+// width's tile shape, at most the grid's waves).  The widths b(a), b in {64, ..., 2048} and never decreasing with
+// the size, are the ones that minimise the task's expected time: the sum over
+// row sizes of band(a) times that cost, plus the launch cost of every width
+// used, band(a) being the task's band pairs of rows of size a.  A dynamic
+// program over the sizes finds them.
+constexpr int kNumAuto = 6;
+constexpr uint32_t kAutoWords[kNumAuto] = {1, 2, 4, 8, 16, 32};  // b = 64 .. 2048
+// the width the verification's cascade test uses (built with the classes)
+constexpr uint32_t kCascadeWords = 8;
+static_assert(sizeof(kFilterNsPerPair) / sizeof(double) == kNumAuto, "one cost per width");
+static_assert(kNumAuto <= (int)kMaxClasses, "every automatic width fits a slot");
 
 struct WidthClass {
   uint32_t max_size;  // rows of size in (previous max_size, max_size]
@@ -635,41 +714,61 @@ struct WidthClass {
 
 // P(false survivor) of a row of size a at each automatic width, per
 // (function, threshold), extended as larger sizes come up.
-std::vector<std::array<double, 4>> false_survivor_odds(uint32_t max_rows, int sim, uint64_t p,
-                                                       uint64_t q) {
+std::vector<std::array<double, kNumAuto>> false_survivor_odds(uint32_t max_rows, int sim,
+                                                              uint64_t p, uint64_t q) {
   static std::mutex mu;
   static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>,
-                  std::vector<std::array<double, 4>>> memo;
+                  std::vector<std::array<double, kNumAuto>>> memo;
   std::lock_guard<std::mutex> lk(mu);
-  std::vector<std::array<double, 4>> &v = memo[{sim, {p, q}}];
-  if (v.empty()) v.push_back({0.0, 0.0, 0.0, 0.0});  // size 0: never pairs
+  std::vector<std::array<double, kNumAuto>> &v = memo[{sim, {p, q}}];
+  if (v.empty()) v.push_back({});  // size 0: never pairs
   for (uint32_t a = (uint32_t)v.size(); a <= max_rows; ++a) {
     const uint64_t L = 2ull * a;
     const int64_t slack = (int64_t)L - 2 * (int64_t)omin_of(sim, a, a, p, q);
-    std::array<double, 4> pr{};
-    for (int k = 0; k < 4; ++k) {
+    std::array<double, kNumAuto> pr{};
+    for (int k = 0; k < kNumAuto; ++k) {
       const double b = 64.0 * kAutoWords[k];
       const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
       pr[k] = binomial_cdf((int)b, pi, slack);
     }
     v.push_back(pr);
   }
-  return std::vector<std::array<double, 4>>(v.begin(), v.begin() + max_rows + 1);
+  return std::vector<std::array<double, kNumAuto>>(v.begin(), v.begin() + max_rows + 1);
 }
 
-// The width classes of a task whose rows of size a hold band[a] band pairs
-// (a = 0 .. band.size() - 1).
-std::vector<WidthClass> choose_classes(const std::vector<double> &band, int sim, uint64_t p,
+// A task's rows of one size: their band pairs and their number.
+struct SizeLoad {
+  double band = 0, rows = 0;
+};
+
+// The width classes of a task whose rows of size a are load[a]
+// (a = 0 .. load.size() - 1).
+std::vector<WidthClass> choose_classes(const std::vector<SizeLoad> &load, int sim, uint64_t p,
                                        uint64_t q) {
-  const uint32_t n = std::max<uint32_t>((uint32_t)band.size() - 1, 1);
+  const uint32_t n = std::max<uint32_t>((uint32_t)load.size() - 1, 1);
   const auto odds = false_survivor_odds(n, sim, p, q);
+  // tile shape of each width's kernel, and the waves of a filter grid
+  double tile_rows[kNumAuto], tile_cols[kNumAuto];
+  for (int k = 0; k < kNumAuto; ++k) {
+    const uint32_t w = kAutoWords[k];
+    tile_rows[k] = std::max<uint32_t>(1, filter_shape(filter_padded_words(w), w < 8).rows);
+    tile_cols[k] = kClassTileCols[k];
+  }
+  const double waves = (double)filter_grid_blocks() * (kBlock / 64);
   // best[a][k]: least cost of sizes 1..a with size a at width k
-  std::vector<std::array<double, 4>> best(n + 1);
-  std::vector<std::array<int8_t, 4>> from(n + 1);
+  std::vector<std::array<double, kNumAuto>> best(n + 1);
+  std::vector<std::array<int8_t, kNumAuto>> from(n + 1);
   for (uint32_t a = 1; a <= n; ++a) {
-    const double w = a < band.size() ? band[a] : 0.0;
-    for (int k = 0; k < 4; ++k) {
-      const double here = w * (kFilterNsPerPair[k] + odds[a][k] * kSurvivorNs);
+    const double w = a < load.size() ? load[a].band : 0.0;
+    const double rows = a < load.size() ? load[a].rows : 0.0;
+    const double cols = rows > 0 ? w / rows : 0.0;  // band columns of a row
+    for (int k = 0; k < kNumAuto; ++k) {
+      const double P = odds[a][k], s = kPairsPerStep[k];
+      const double step_hit = -std::expm1(s * std::log1p(-std::min(P, 1.0 - 1e-16)));
+      const double tiles = std::min(waves, std::max(1.0, rows / tile_rows[k]) *
+                                               std::max(1.0, std::ceil(cols / tile_cols[k])));
+      const double surv = std::max(kSurvivorNs, kSurvivorWaveNs[k] / tiles);
+      const double here = w * (kFilterNsPerPair[k] + step_hit * kSlowEntryNs / s + P * surv);
       if (a == 1) {
         best[a][k] = here + kClassLaunchNs[k];
         from[a][k] = (int8_t)k;
@@ -687,7 +786,7 @@ std::vector<WidthClass> choose_classes(const std::vector<double> &band, int sim,
     }
   }
   int k = 0;
-  for (int j = 1; j < 4; ++j)
+  for (int j = 1; j < kNumAuto; ++j)
     if (best[n][j] < best[n][k]) k = j;
   std::vector<uint32_t> width(n + 1, kAutoWords[0]);
   for (uint32_t a = n; a >= 1; --a) {
@@ -703,24 +802,26 @@ std::vector<WidthClass> choose_classes(const std::vector<double> &band, int sim,
 }
 
 // Band pairs of a task's rows of each size (Table 2's length band; a
-// self-join counts each unordered pair once, same-size pairs included).
-std::vector<double> band_by_size(const Space &R, const Space &C, int sim, uint64_t p, uint64_t q,
-                                 uint32_t row_side, uint32_t col_side, bool self) {
+// self-join counts each unordered pair once, same-size pairs included), and
+// the rows of each size.
+std::vector<SizeLoad> band_by_size(const Space &R, const Space &C, int sim, uint64_t p,
+                                   uint64_t q, uint32_t row_side, uint32_t col_side, bool self) {
   const uint32_t a_max = R.side_max[row_side], c_max = C.side_max[col_side];
   const uint32_t *rs = R.ss(row_side), *cs = C.ss(col_side);
-  std::vector<double> w((size_t)a_max + 1, 0.0);
+  std::vector<SizeLoad> w((size_t)a_max + 1);
   for (uint32_t a = 1; a <= a_max; ++a) {
     const double nr = (double)rs[a + 1] - (double)rs[a];
     if (nr <= 0) continue;
+    w[a].rows = nr;
     uint64_t lo = 0, hi = 0;
     size_band(sim, a, p, q, lo, hi);
     hi = std::min<uint64_t>(hi, c_max);
     if (self) hi = std::min<uint64_t>(hi, a);
     if (lo > hi) continue;
     if (self && hi == a) {
-      w[a] = nr * ((double)cs[a] - (double)cs[lo]) + nr * (nr - 1) / 2;
+      w[a].band = nr * ((double)cs[a] - (double)cs[lo]) + nr * (nr - 1) / 2;
     } else {
-      w[a] = nr * ((double)cs[hi + 1] - (double)cs[lo]);
+      w[a].band = nr * ((double)cs[hi + 1] - (double)cs[lo]);
     }
   }
   return w;
@@ -821,13 +922,13 @@ struct Plan {
   // per width slot: its tiles [tile_lo[k], tile_hi[k]), padded width, work,
   // and whether the matrix-core kernel runs it
   uint32_t n_slots = 0;
-  bool slot_mfma[kMaxClasses] = {false, false, false, false};
-  uint32_t slot_words[kMaxClasses] = {0, 0, 0, 0};
-  uint32_t slot_bits[kMaxClasses] = {0, 0, 0, 0};
-  uint32_t slot_max_size[kMaxClasses] = {0, 0, 0, 0};
-  uint32_t tile_lo[kMaxClasses] = {0, 0, 0, 0}, tile_hi[kMaxClasses] = {0, 0, 0, 0};
-  uint32_t slot_tile_cols[kMaxClasses] = {0, 0, 0, 0};
-  uint64_t ops[kMaxClasses] = {0, 0, 0, 0};
+  bool slot_mfma[kMaxClasses] = {};
+  uint32_t slot_words[kMaxClasses] = {};
+  uint32_t slot_bits[kMaxClasses] = {};
+  uint32_t slot_max_size[kMaxClasses] = {};
+  uint32_t tile_lo[kMaxClasses] = {}, tile_hi[kMaxClasses] = {};
+  uint32_t slot_tile_cols[kMaxClasses] = {};
+  uint64_t ops[kMaxClasses] = {};
 };
 
 // The task's threshold tables, appended to pl.tables.
@@ -976,7 +1077,7 @@ struct Timer {
 // ------------------------------------------------------------------- join
 
 struct JoinOut {
-  ssj_pair *pairs = nullptr;            // host, malloc
+  ssj_pair *pairs = nullptr;            // host, HostPairs
   uint64_t count = 0;
   std::vector<uint64_t> task_start;     // [n_tasks + 1]
 };
@@ -1048,7 +1149,7 @@ void launch_round(const JoinRun &jr, FilterConfig cfg, uint2 *queue, uint64_t qc
     cfg.tile_hi = pl.tile_hi[k];
     cfg.tile_cols = pl.slot_tile_cols[k];
     cfg.cls = k;
-    cfg.chunk = jr.automatic && pl.slot_words[k] < kAutoWords[3] ? kFilterStage : dense_chunk;
+    cfg.chunk = jr.automatic && pl.slot_words[k] < kCascadeWords ? kFilterStage : dense_chunk;
     const uint32_t w = pl.slot_words[k];
     const bool mf = pl.slot_mfma[k], cos = jr.any_cosine;
     const FilterArgs fa{R.bitmaps(w), C.bitmaps(w), mf ? R.signs(w) : nullptr,
@@ -1070,12 +1171,13 @@ void launch_round(const JoinRun &jr, FilterConfig cfg, uint2 *queue, uint64_t qc
   const VerifySpace vr = jr.vrows, vc = jr.vcols;
   const uint32_t *side_task = jr.d_side_task, *tables = jr.d_tables, w2 = jr.w2;
   const TaskDesc *tasks = jr.d_tasks;
+  const uint32_t n_tasks = jr.n_tasks;
   const int ib = jr.ib, jb = jr.jb;
   const uint32_t so = jr.jc.survivors_only ? 1u : 0u;
   JoinCounters *ctr = jr.ctr;
   go(L, st, [=](hipStream_t s) {
-    return launch_verify(queue, qcap, vr, vc, side_task, tasks, tables, ib, jb, so, w2, results,
-                         res_cap, ctr, s);
+    return launch_verify(queue, queue + qcap, qcap, vr, vc, side_task, tasks, n_tasks, tables,
+                         ib, jb, so, w2, results, res_cap, ctr, s);
   });
   if (tm) check(hipEventRecord(tm->verify.back().ev[1], st));
 }
@@ -1166,7 +1268,7 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   // band pairs of each slot, and its kernel: the matrix cores where the
   // width has a matrix-core shape, unless it is a small b = 256 class (see
   // kMfmaMinBand) and the caller did not ask for them
-  uint64_t slot_band[kMaxClasses] = {0, 0, 0, 0};
+  uint64_t slot_band[kMaxClasses] = {};
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     for (uint32_t t = 0; t < n_tasks; ++t) {
       uint32_t prev = 0;
@@ -1188,10 +1290,12 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
     bw[nbw] = pl.slot_words[k];
     bb[nbw++] = pl.slot_bits[k];
   }
-  if (automatic && !jc.survivors_only && pl.n_slots > 0 &&
-      pl.slot_words[pl.n_slots - 1] < kAutoWords[3]) {
-    bw[nbw] = kAutoWords[3];
-    bb[nbw++] = 64 * kAutoWords[3];
+  bool have_cascade = false;
+  for (uint32_t k = 0; k < nbw; ++k) have_cascade |= bw[k] == kCascadeWords;
+  if (automatic && !jc.survivors_only && pl.n_slots > 0 && pl.slot_words[0] < kCascadeWords &&
+      !have_cascade) {
+    bw[nbw] = kCascadeWords;
+    bb[nbw++] = 64 * kCascadeWords;
   }
   // a resident space (an index's) already holds every width it may need
   for (uint32_t k = 0; k < nbw; ++k) {
@@ -1226,7 +1330,7 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
     uint32_t tile_cols = jc.tile_cols;
     if (!jc.tile_cols_fixed && automatic) {
       // the measured best tile width of the class's width
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < kNumAuto; ++a)
         if (kAutoWords[a] == pl.slot_words[k]) tile_cols = kClassTileCols[a];
     }
     if (!jc.tile_cols_fixed) {
@@ -1343,7 +1447,8 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
   uint32_t dense_chunk =
       (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
-  uint2 *queue = ar.alloc<uint2>(qcap);
+  // the queue, then as many slots for the long pairs verification defers
+  uint2 *queue = ar.alloc<uint2>(2 * qcap);
   const uint32_t max_waves = (uint32_t)filter_grid_blocks() * (kBlock / 64);
   Resume *res_a = ar.alloc<Resume>(max_waves), *res_b = ar.alloc<Resume>(max_waves);
   uint64_t res_cap = std::max<uint64_t>(qcap, 1024);
@@ -1358,7 +1463,8 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   // narrowest class (a second test before every merge)
   uint32_t w2 = 0;
   for (uint32_t k = 0; k < R.n_bm; ++k)
-    if (R.bm_words[k] > w2 && C.bitmaps(R.bm_words[k])) w2 = R.bm_words[k];
+    if (R.bm_words[k] > w2 && R.bm_words[k] <= kCascadeWords && C.bitmaps(R.bm_words[k]))
+      w2 = R.bm_words[k];
   const bool cascade = automatic && !jc.survivors_only && pl.n_slots > 0 && w2 > pl.slot_words[0];
   // wide bitmaps for pairs of large sets (automatic mode, as the cascade);
   // an index holds its own
@@ -1437,20 +1543,21 @@ void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Time
   FilterConfig cfg = jr.cfg;
   float prefix_ms_index = 0, prefix_ms_verify = 0;
   uint64_t prefix_candidates = 0;
-  uint64_t results_n = 0;
+  uint64_t results_n = 0, queue_slots = 0;
   JoinCounters ctr_h{};
   if (pl.n_tiles) {
     for (;;) {
       d2h(&ctr_h, ctr, 1, st);
       sync(st);
       if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
+      queue_slots += std::min<uint64_t>(ctr_h.queue_count, qcap);
       results_n = ctr_h.results;
       if (results_n > res_cap) throw Fail{SSJ_E_DEVICE};  // cannot happen: capacity grows first
       if (!ctr_h.overflow) break;
       // drain done; a queue the library sized itself grows for the next round
       if (!jc.cap_fixed && qcap < std::min<uint64_t>(kMaxQueue, pl.band_pairs + 1)) {
         qcap = std::min<uint64_t>(std::min<uint64_t>(kMaxQueue, pl.band_pairs + 1), 4 * qcap);
-        queue = ar.alloc<uint2>(qcap);
+        queue = ar.alloc<uint2>(2 * qcap);
         dense_chunk =
             (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(kFilterStage, qcap / 64));
       }
@@ -1522,7 +1629,7 @@ void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Time
     unsigned long long *cand = ar.alloc<unsigned long long>(ccap);
     unsigned long long *ctmp = ar.alloc<unsigned long long>(ccap);
     uint32_t *cscr = ar.alloc<uint32_t>(radix_scratch_words(ccap));
-    uint2 *pqueue = ccap > qcap ? ar.alloc<uint2>(ccap) : queue;
+    uint2 *pqueue = ccap > qcap ? ar.alloc<uint2>(2 * ccap) : queue;
     int cshifts[8], ncs = 0;
     const int bs = std::max(1, bits_for(C.n ? C.n - 1 : 0)), br = std::max(1, bits_for(R.n ? R.n - 1 : 0));
     for (int b = 0; b < bs; b += 8) cshifts[ncs++] = b;
@@ -1545,9 +1652,9 @@ void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Time
           results = nr;
           res_cap = ncap;
         }
-        check(launch_verify(pqueue, ccap, vrows, vcols, d_side_task, d_tasks, d_tables, ib, jb,
-                            jc.survivors_only ? 1u : 0u, w2, results, res_cap, ctr,
-                        st));
+        check(launch_verify(pqueue, pqueue + ccap, ccap, vrows, vcols, d_side_task, d_tasks,
+                            n_tasks, d_tables, ib, jb, jc.survivors_only ? 1u : 0u, w2, results,
+                            res_cap, ctr, st));
         d2h(&ctr_h, ctr, 1, st);
         sync(st);
         if (ctr_h.error & kErrUnsorted) throw Fail{SSJ_E_UNSORTED};
@@ -1577,7 +1684,7 @@ void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Time
     ssj_pair *dpairs = ar.alloc<ssj_pair>(results_n);
     uint64_t *dstart = ar.alloc<uint64_t>(n_tasks + 1);
     check(launch_split_results(sorted, results_n, ib, jb, n_tasks, dpairs, dstart, st));
-    jo.pairs = static_cast<ssj_pair *>(std::malloc(results_n * sizeof(ssj_pair)));
+    jo.pairs = HostPairs::get().alloc(results_n);
     if (!jo.pairs) throw Fail{SSJ_E_NOMEM};
     jo.count = results_n;
     d2h(jo.pairs, dpairs, results_n, st);
@@ -1592,11 +1699,13 @@ void join_end(const JoinRun &jr, Arena &ar, hipStream_t st, RoundTimes &tm, Time
     stats->filter_launches = tm.launches;
     stats->b_bits = jc.b_bits;
     stats->filter_ops = pl.filter_ops;
+    stats->queue_slots = queue_slots;
     stats->n_classes = pl.n_slots;
     for (uint32_t k = 0; k < pl.n_slots; ++k) {
       stats->class_bits[k] = pl.slot_bits[k];
       stats->class_max_size[k] = pl.slot_max_size[k];
       stats->class_ops[k] = pl.ops[k];
+      stats->class_tiles[k] = pl.tile_hi[k] - pl.tile_lo[k];
     }
     stats->ms_prepare = t_prep ? t_prep->ms() : 0.f;
     float gms = 0;
@@ -1706,11 +1815,11 @@ int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const u
     std::vector<TaskIn> tasks{{0, 0, sim, p, q, self}};
     run_join(A, C, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     (void)hipGetLastError();
     return f.code;
   } catch (const std::bad_alloc &) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     return SSJ_E_NOMEM;
   }
   out->pairs = jo.pairs;
@@ -1804,11 +1913,11 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
     space_finish(A);
     run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     (void)hipGetLastError();
     return f.code;
   } catch (const std::bad_alloc &) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     return SSJ_E_NOMEM;
   }
   out->pairs = jo.pairs;
@@ -2038,9 +2147,9 @@ int ssj_index_create(const ssj_sets *s, uint32_t b_bits, ssj_index **out, void *
       if (b_bits) {
         space_bitmaps(idx->S, wfix, b_bits, idx->ar, ctr, st);
       } else {
-        uint32_t bits[4];
-        for (int k = 0; k < 4; ++k) bits[k] = 64 * kAutoWords[k];
-        space_bitmaps_multi(idx->S, kAutoWords, bits, 4, idx->ar, ctr, st);
+        uint32_t bits[kNumAuto];
+        for (int k = 0; k < kNumAuto; ++k) bits[k] = 64 * kAutoWords[k];
+        space_bitmaps_multi(idx->S, kAutoWords, bits, kNumAuto, idx->ar, ctr, st);
       }
       // sign planes of every width the matrix-core filter runs, and wide
       // bitmaps of its large sets for verification
@@ -2168,11 +2277,11 @@ int ssj_plan_execute(ssj_plan *plan, ssj_pairs *out, uint64_t *starts, ssj_stats
     check(hipEventRecord(plan->ev[1], st));
     join_end(plan->jr, tmp, st, tm, nullptr, jo, stats);
   } catch (const Fail &f) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     (void)hipGetLastError();
     return f.code;
   } catch (const std::bad_alloc &) {
-    std::free(jo.pairs);
+    HostPairs::get().release(jo.pairs);
     return SSJ_E_NOMEM;
   }
   out->pairs = jo.pairs;
@@ -2205,7 +2314,7 @@ int ssj_cutoff(uint32_t b_bits, int method, int sim, uint32_t p, uint32_t q, uin
 
 void ssj_free_pairs(ssj_pairs *out) {
   if (!out) return;
-  std::free(out->pairs);
+  ssj::HostPairs::get().release(out->pairs);
   out->pairs = nullptr;
   out->count = 0;
 }

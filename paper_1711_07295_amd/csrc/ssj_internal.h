@@ -22,13 +22,14 @@ constexpr int kBlock = 256;
 constexpr uint32_t kXcds = 8;   // XCDs of an MI355X (workgroups go to them round-robin)
 constexpr uint32_t kParts = 64; // tile cursors per width class, kParts / kXcds per XCD
 // Width classes of one join (one filter launch each).
-constexpr uint32_t kMaxClasses = 4;
+constexpr uint32_t kMaxClasses = 6;
 
 // Counters of one filter/verify round, in device memory.
 struct JoinCounters {
   unsigned long long queue_count;   // slots reserved in the survivor queue
   unsigned long long survivors;     // real survivors seen by verification
   unsigned long long results;       // pairs written to the result buffer
+  unsigned long long long_count;    // long pairs deferred by this round's verification
   uint32_t overflow;                // the queue filled during this filter launch
   uint32_t n_resume;                // resume entries written this launch
   uint32_t error;                   // validation error bits (kErr*)
@@ -196,12 +197,13 @@ hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uin
 // output is in caller order (row base_s + k for caller set k); with them, in
 // size order (row g for the set perm[g] of side side_of[g]).  The strict
 // token order of every set is checked on the way.
-// fold (optional): also write the widths out_words/2, /4, /8 (out[k] for
-// out_words >> (k+1) words; NULL entries skipped) from the same pass; needs
-// a power-of-two width of at most 8 words, Xor or Set, and the segmented
-// build (caller order, or size order through rank).
+// fold (optional): also write the widths out_words/2, /4, ..., /32 (out[k]
+// for out_words >> (k+1) words; NULL entries skipped) from the same pass;
+// needs a power-of-two width of at most kMaxFoldWords words, Xor or Set, and
+// the segmented build (caller order, or size order through rank).
+constexpr uint32_t kMaxFoldWords = 32;
 struct FoldOut {
-  uint64_t *out[3];
+  uint64_t *out[5];
 };
 hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_t seg_blocks,
                                 uint64_t n_total, const uint32_t *perm, const uint32_t *rank,
@@ -315,14 +317,19 @@ struct VerifySpace {
 // into 64-bit result keys (task << (ib + jb)) | (i << jb) | j of caller
 // indices (self-join pairs as (min, max)).  side_task[s]: the task of row
 // side s.
-// w2: words of the cascade bitmaps (rows.bm2 and cols.bm2 both set, or
-// both NULL for no second test); rows.bmw and cols.bmw likewise for the
-// wide test.
-hipError_t launch_verify(const uint2 *queue, unsigned long long cap, VerifySpace rows,
-                         VerifySpace cols, const uint32_t *side_task, const TaskDesc *tasks,
-                         const uint32_t *tables, int ib, int jb, uint32_t survivors_only,
-                         uint32_t w2, unsigned long long *results,
-                         unsigned long long results_cap, JoinCounters *ctr, hipStream_t st);
+// w2: words of the cascade bitmaps, 2, 4 or 8 (rows.bm2 and cols.bm2 both
+// set, or both NULL for no second test); rows.bmw and cols.bmw likewise for
+// the wide test.  n_tasks: tasks of the call (>= 1); the column of an entry
+// lies in its task's column side.
+// longq (optional, cap entries, ctr->long_count zero): the pairs of long
+// sets that pass the bitmap tests are merged there by whole waves, in a
+// second launch on the same stream.
+hipError_t launch_verify(const uint2 *queue, uint2 *longq, unsigned long long cap,
+                         VerifySpace rows, VerifySpace cols, const uint32_t *side_task,
+                         const TaskDesc *tasks, uint32_t n_tasks, const uint32_t *tables, int ib,
+                         int jb, uint32_t survivors_only, uint32_t w2,
+                         unsigned long long *results, unsigned long long results_cap,
+                         JoinCounters *ctr, hipStream_t st);
 
 // Sorted result keys -> ssj_pair {i, j}; task_start[k] = first result of
 // task k (k in [0, n_tasks]).

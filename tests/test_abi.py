@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version_and_status_strings():
-    assert ssj.ssj_abi_version() == 3
+    assert ssj.ssj_abi_version() == ssj.ABI_VERSION == 4
     assert ssj.status_string(0) == "ok"
     assert "strictly increasing" in ssj.status_string(ssj.SSJ_E_UNSORTED)
     assert ssj.status_string(12345) == "unknown status"
@@ -57,7 +57,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ssj.ssj_pair) == 8
     assert ctypes.sizeof(ssj.ssj_pairs) == 16
     assert ctypes.sizeof(ssj.ssj_options) == 16
-    assert ctypes.sizeof(ssj.ssj_stats) == 8 * 4 + 4 * 3 + 4 * 8 + 4 + 8 * 4 + 4 * 4 + 4 * 5 + 4
+    assert ctypes.sizeof(ssj.ssj_stats) == 8 * 5 + 4 * 3 + 4 * 16 + 4 + 8 * 8 + 8 * 8 + 4 * 8 + 4 * 5 + 4
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -31,3 +31,28 @@ def test_valu_roofline_and_odd_widths():
     r = bench.roofline_of([st], 1, valu=True)
     assert r["bound"] == "alu" and math.isclose(r["ops_per_launch"], 2500)
     assert math.isclose(r["frac"], 5000 / 1e-3 / bench.PEAK_INT_OPS)
+
+
+def test_zero_event_timings_give_no_roofline_entry():
+    st = _stats([64], [5000], [0.0])
+    assert bench.roofline_of([st], 1) is None
+
+
+def test_golden_parity_compares_the_pair_list_hash():
+    import json
+    import os
+
+    import numpy as np
+    path = os.path.join(bench.ROOT, "tests", "golden", "full_golden.json")
+    if not os.path.exists(path):
+        import pytest
+        pytest.skip("no full-size golden pair lists")
+    with open(path) as fh:
+        entry = json.load(fh)["selfjoin-1m"]
+    ck = int(entry["checksum"], 16)
+    pairs = np.zeros((3, 2), dtype=np.uint32)
+    r = bench.golden_parity("selfjoin-1m", ck, "jaccard", 4, 5, pairs)
+    assert r["sha256_equal"] is False and r["expected_pairs"] == entry["thresholds"]["4/5"]["pairs"]
+    assert bench.golden_parity("selfjoin-1m", ck + 1, "jaccard", 4, 5, pairs) is None
+    assert bench.golden_parity("selfjoin-1m", ck, "dice", 4, 5, pairs) is None
+    assert bench.golden_parity("selfjoin-1m", ck, "jaccard", 3, 5, pairs) is None

@@ -38,7 +38,8 @@ def test_self_join_with_cutoff_matches_oracle(b, pq):
     assert np.array_equal(got, want), (b, p, q, len(got), len(want))
     # the band is the same; the bitmap filter does less work
     assert st["band_pairs"] == st0["band_pairs"] == oracle.band_pairs(c.sizes(), p, q)
-    omega = ssj.ssj_cutoff(b or 512, p, q)
+    # the widest width the automatic mode chose: its cutoff point
+    omega = ssj.ssj_cutoff(b or st0["class_bits"][st0["n_classes"] - 1], p, q)
     if c.sizes().max() > omega:
         assert st["filter_ops"] < st0["filter_ops"]
 

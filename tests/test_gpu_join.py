@@ -238,7 +238,7 @@ def test_automatic_width_classes_match_oracle(pq):
     assert st["b_bits"] == 0 and st["n_classes"] >= 1
     assert st["band_pairs"] == oracle.band_pairs(c.sizes(), p, q)
     bits = st["class_bits"][:st["n_classes"]]
-    assert bits == sorted(bits) and set(bits) <= {64, 128, 256, 512}
+    assert bits == sorted(bits) and set(bits) <= {64, 128, 256, 512, 1024, 2048}
     sizes = st["class_max_size"][:st["n_classes"]]
     assert sizes == sorted(sizes) and sizes[-1] == int(c.sizes().max())
     # the filter's algorithmic work lies between the narrowest and widest class
