@@ -91,72 +91,87 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps(
   if (__ballot(unsorted) && lane == 0) atomicOr(&ctr->error, kErrUnsorted);
 }
 
-// Narrow bitmaps (up to 8 words), XOR or SET: a workgroup takes kSegSets
-// consecutive sets in caller order, whose tokens are one contiguous run of
-// the CSR array, and reads that run fully coalesced.  Each token finds its
+// Bitmaps of up to 8 words, and of 16 and 32, XOR or SET: a workgroup takes
+// kSegSets consecutive sets in caller order, whose tokens are one contiguous
+// run of the CSR array, and reads that run fully coalesced (in passes of as
+// many sets as 16 KB of LDS bitmaps hold).  Each token finds its
 // set by binary search over the segment's offsets in LDS and flips (or sets)
 // its bit in the set's LDS bitmap; the bitmaps are then written to their
 // output rows (rank[k] when the output is in size order).
 constexpr uint32_t kSegSets = 256;
+
+// Sets of a segment one pass of the build holds in LDS: 16 KB of bitmaps
+// (256 sets up to 8 words, 128 at 16 words, 64 at 32), so that wide widths
+// keep as many workgroups per compute unit as narrow ones.
+template <int WO>
+constexpr uint32_t seg_pass_sets() {
+  return kSegSets * 8 / (WO > 8 ? WO : 8);
+}
 
 template <int WO, int METHOD, bool POW2>
 __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
     const SideDesc *__restrict__ sides, uint32_t n_sides, const uint32_t *__restrict__ rank,
     uint64_t n, uint32_t b_bits, uint64_t *__restrict__ out, FoldOut fold,
     JoinCounters *__restrict__ ctr) {
-  __shared__ uint64_t soff[kSegSets + 1];
-  __shared__ uint32_t sbits[kSegSets * 2 * WO];
+  constexpr uint32_t kPass = seg_pass_sets<WO>();
+  __shared__ uint64_t soff[kPass + 1];
+  __shared__ uint32_t sbits[kPass * 2 * WO];
   const SideDesc sd = sides[side_of_block(sides, n_sides, blockIdx.x)];
-  const uint64_t s0 = (uint64_t)(blockIdx.x - sd.blk0) * kSegSets;
-  if (s0 >= sd.n) return;  // whole workgroup leaves together
-  const uint32_t ns = (uint32_t)min((uint64_t)kSegSets, sd.n - s0);
+  const uint64_t seg0 = (uint64_t)(blockIdx.x - sd.blk0) * kSegSets;
+  if (seg0 >= sd.n) return;  // whole workgroup leaves together
+  const uint32_t nseg = (uint32_t)min((uint64_t)kSegSets, sd.n - seg0);
   const uint64_t *__restrict__ offsets = sd.offsets;
   const uint32_t *__restrict__ tokens = sd.tokens;
-  const uint64_t t0 = offsets[s0];
-  for (uint32_t i = threadIdx.x; i <= ns; i += kBlock) soff[i] = offsets[s0 + i] - t0;
-  for (uint32_t i = threadIdx.x; i < ns * 2 * WO; i += kBlock) sbits[i] = 0;
-  __syncthreads();
-  const uint64_t nt = soff[ns];
   const uint32_t mask = b_bits - 1;
   bool unsorted = false;
-  for (uint64_t g = threadIdx.x; g < nt; g += kBlock) {
-    uint32_t lo = 0, hi = ns;  // soff[lo] <= g < soff[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (soff[mid] <= g) lo = mid; else hi = mid;
-    }
-    const uint32_t v = tokens[t0 + g];
-    if (g + 1 < soff[lo + 1]) unsorted |= !(v < tokens[t0 + g + 1]);
-    const uint32_t s = POW2 ? (v & mask) : (v % b_bits);
-    if (METHOD == SSJ_BM_XOR) atomicXor(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
-    else atomicOr(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < ns * WO; i += kBlock) {
-    const uint32_t x = i / WO, w = i - x * WO;
-    const uint64_t row = rank ? rank[sd.base + s0 + x] : sd.base + s0 + x;
-    if (row < n)
-      out[row * WO + w] = (uint64_t)sbits[x * 2 * WO + 2 * w] |
-                          ((uint64_t)sbits[x * 2 * WO + 2 * w + 1] << 32);
-  }
-  // Narrower widths b' = b / 2^k from the same pass: bit k' of b' collects
-  // the tokens with t mod b' = k', i.e. bits k' + m b' of b, so word i of b'
-  // combines (xor for Bitmap-Xor, or for Bitmap-Set) words i + m (b'/64).
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    const uint32_t wf = (uint32_t)WO >> (f + 1);
-    if (wf == 0 || fold.out[f] == nullptr) continue;
-    for (uint32_t i = threadIdx.x; i < ns * wf; i += kBlock) {
-      const uint32_t x = i / wf, w = i - x * wf;
-      uint64_t v = 0;
-      for (uint32_t m = 0; m < (uint32_t)WO / wf; ++m) {
-        const uint32_t src = w + m * wf;
-        const uint64_t word = (uint64_t)sbits[x * 2 * WO + 2 * src] |
-                              ((uint64_t)sbits[x * 2 * WO + 2 * src + 1] << 32);
-        v = METHOD == SSJ_BM_XOR ? (v ^ word) : (v | word);
+  for (uint32_t p0 = 0; p0 < nseg; p0 += kPass) {
+    const uint64_t s0 = seg0 + p0;
+    const uint32_t ns = min(kPass, nseg - p0);
+    const uint64_t t0 = offsets[s0];
+    if (p0) __syncthreads();  // the previous pass has read soff and sbits
+    for (uint32_t i = threadIdx.x; i <= ns; i += kBlock) soff[i] = offsets[s0 + i] - t0;
+    for (uint32_t i = threadIdx.x; i < ns * 2 * WO; i += kBlock) sbits[i] = 0;
+    __syncthreads();
+    const uint64_t nt = soff[ns];
+    for (uint64_t g = threadIdx.x; g < nt; g += kBlock) {
+      uint32_t lo = 0, hi = ns;  // soff[lo] <= g < soff[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (soff[mid] <= g) lo = mid; else hi = mid;
       }
+      const uint32_t v = tokens[t0 + g];
+      if (g + 1 < soff[lo + 1]) unsorted |= !(v < tokens[t0 + g + 1]);
+      const uint32_t s = POW2 ? (v & mask) : (v % b_bits);
+      if (METHOD == SSJ_BM_XOR) atomicXor(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+      else atomicOr(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ns * WO; i += kBlock) {
+      const uint32_t x = i / WO, w = i - x * WO;
       const uint64_t row = rank ? rank[sd.base + s0 + x] : sd.base + s0 + x;
-      if (row < n) fold.out[f][row * wf + w] = v;
+      if (row < n)
+        out[row * WO + w] = (uint64_t)sbits[x * 2 * WO + 2 * w] |
+                            ((uint64_t)sbits[x * 2 * WO + 2 * w + 1] << 32);
+    }
+    // Narrower widths b' = b / 2^k from the same pass: bit k' of b' collects
+    // the tokens with t mod b' = k', i.e. bits k' + m b' of b, so word i of
+    // b' combines (xor for Bitmap-Xor, or for Bitmap-Set) words i + m (b'/64).
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const uint32_t wf = (uint32_t)WO >> (f + 1);
+      if (wf == 0 || fold.out[f] == nullptr) continue;
+      for (uint32_t i = threadIdx.x; i < ns * wf; i += kBlock) {
+        const uint32_t x = i / wf, w = i - x * wf;
+        uint64_t v = 0;
+        for (uint32_t m = 0; m < (uint32_t)WO / wf; ++m) {
+          const uint32_t src = w + m * wf;
+          const uint64_t word = (uint64_t)sbits[x * 2 * WO + 2 * src] |
+                                ((uint64_t)sbits[x * 2 * WO + 2 * src + 1] << 32);
+          v = METHOD == SSJ_BM_XOR ? (v ^ word) : (v | word);
+        }
+        const uint64_t row = rank ? rank[sd.base + s0 + x] : sd.base + s0 + x;
+        if (row < n) fold.out[f][row * wf + w] = v;
+      }
     }
   }
   if (__ballot(unsorted) && (threadIdx.x & 63) == 0) atomicOr(&ctr->error, kErrUnsorted);

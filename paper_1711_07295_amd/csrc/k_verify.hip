@@ -390,8 +390,13 @@ __global__ __launch_bounds__(kBlock) void k_verify(const uint2 *__restrict__ que
   if (threadIdx.x == 0 && block_surv) atomicAdd(&ctr->survivors, (unsigned long long)block_surv);
 }
 
-// The deferred long pairs (their bitmap tests passed): one wave per pair,
-// the pairs dealt to the waves in turn.
+// The deferred long pairs (their bitmap tests passed).  A few of them (up to
+// kLaneMode per wave): one wave per pair, the pairs dealt to the waves in
+// turn, so that each takes a few round trips.  Many: a lane per pair, 64 at
+// a time, which takes longer per pair but costs the wave less (a wave's
+// merge of one pair is about eight times the work of a lane's).
+constexpr uint32_t kLaneMode = 8;
+
 template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_verify_long(unsigned long long cap, VerifyArgs va,
                                                         unsigned long long *__restrict__ results,
@@ -404,6 +409,41 @@ __global__ __launch_bounds__(kBlock) void k_verify_long(unsigned long long cap, 
   const unsigned long long wave = (unsigned long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const OneTask one = ONE ? one_task(va) : OneTask{};
   const VerifySpace &rows = va.rows, &cols = va.cols;
+  if (count >= (unsigned long long)kLaneMode * n_waves) {
+    for (unsigned long long e0 = wave * 64; e0 < count; e0 += n_waves * 64) {
+      const unsigned long long e = e0 + lane;
+      bool hit = false;
+      unsigned long long key = 0;
+      if (e < count) {
+        const uint2 qe = va.longq[e];
+        const uint32_t x = qe.x, y = qe.y;
+        const uint32_t sr = ONE ? 0u : rows.side_of[x], sc = ONE ? 0u : cols.side_of[y];
+        const uint32_t px = rows.perm[x], py = cols.perm[y];
+        const uint32_t a = rows.sizes[x], c = cols.sizes[y];
+        const uint32_t task = ONE ? 0u : va.side_task[sr];
+        const TaskDesc td = ONE ? one.td : va.tasks[task];
+        const uint32_t need = td.sim == SSJ_SIM_COSINE ? cosine_omin(a, c, td.p, td.q)
+                                                       : va.tables[td.omin_off + a + c];
+        const uint64_t r0 = ONE ? one.r_off[px] : rows.sides[sr].offsets[px];
+        const uint64_t s0 = ONE ? one.c_off[py] : cols.sides[sc].offsets[py];
+        const uint32_t *rt = ONE ? one.r_tok : rows.sides[sr].tokens;
+        const uint32_t *ct = ONE ? one.c_tok : cols.sides[sc].tokens;
+        hit = overlap_reaches(rt + r0, a, ct + s0, c, need);
+        if (hit) key = result_key(px, py, td, task, va.ib, va.jb);
+      }
+      const unsigned long long m = __ballot(hit);
+      if (m) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&ctr->results, (unsigned long long)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (hit) {
+          const unsigned long long pos = base + (unsigned long long)__popcll(m & __lanemask_lt());
+          if (pos < results_cap) results[pos] = key;
+        }
+      }
+    }
+    return;
+  }
   for (unsigned long long e = wave; e < count; e += n_waves) {
     const uint2 qe = va.longq[e];
     const uint32_t x = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);

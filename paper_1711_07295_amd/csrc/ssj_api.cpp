@@ -14,17 +14,20 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <functional>
 #include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "autotune_table.h"
@@ -48,6 +51,11 @@ constexpr uint32_t kDefaultTileCols = 2048;
 // few columns, and the launch lasts as long as its slowest tile.  (The
 // matrix-core kernel measured no gain below 64: it takes 32 columns a step.)
 constexpr uint64_t kMinSlotTiles = 16384;
+// Host threads that plan the width classes of a call's tasks (16 tasks or
+// more per thread), when the tasks' largest sizes sum to kPlanThreadSizes
+// or more.
+constexpr uint32_t kPlanThreads = 8;
+constexpr uint64_t kPlanThreadSizes = 65536;
 constexpr uint32_t kMinTileCols = 64;
 constexpr uint32_t kMinTileColsValu = 32;
 // A b = 256 class (four words) of fewer band pairs than this runs on the
@@ -661,16 +669,25 @@ void size_band(int sim, uint64_t a, uint64_t p, uint64_t q, uint64_t &lo, uint64
   lo = std::max<uint64_t>(lo, 1);
 }
 
-// P(X <= k) for X ~ Binomial(n, pi), summed in log space.
+// P(X <= k) for X ~ Binomial(n, pi) with pi <= 1/2, summed in log space
+// over the terms within 12 standard deviations of the mean.  By Chernoff's
+// bound the lower tail beyond that holds less than exp(-36) of the mass
+// (pi <= 1/2); the upper tail's share is also small next to what a cost
+// model can use, so a k beyond either end gives 0 or 1.
 double binomial_cdf(int n, double pi, int64_t k) {
   if (k < 0) return 0.0;
   if (k >= n) return 1.0;
   if (pi <= 0.0) return 1.0;
   if (pi >= 1.0) return 0.0;
+  const double mean = n * pi, sd = std::sqrt(n * pi * (1.0 - pi));
+  if ((double)k < mean - 12.0 * sd) return 0.0;
+  if ((double)k > mean + 12.0 * sd) return 1.0;
+  const int64_t i0 = std::max<int64_t>(0, (int64_t)std::floor(mean - 12.0 * sd));
   const double lp = std::log(pi), lq = std::log1p(-pi);
-  double acc = 0.0, lc = 0.0;  // log C(n, i)
-  for (int64_t i = 0; i <= k; ++i) {
-    if (i > 0) lc += std::log((double)(n - i + 1)) - std::log((double)i);
+  double lc = std::lgamma(n + 1.0) - std::lgamma(i0 + 1.0) - std::lgamma((double)(n - i0) + 1.0);
+  double acc = 0.0;
+  for (int64_t i = i0; i <= k; ++i) {
+    if (i > i0) lc += std::log((double)(n - i + 1)) - std::log((double)i);
     acc += std::exp(lc + i * lp + (n - i) * lq);
   }
   return std::min(acc, 1.0);
@@ -712,28 +729,36 @@ struct WidthClass {
   uint32_t words;
 };
 
-// P(false survivor) of a row of size a at each automatic width, per
-// (function, threshold), extended as larger sizes come up.
-std::vector<std::array<double, kNumAuto>> false_survivor_odds(uint32_t max_rows, int sim,
-                                                              uint64_t p, uint64_t q) {
+// Per row size a and automatic width: P, the chance of a false survivor,
+// and the part of a band pair's cost that does not depend on the task
+// (filter time and slow-path entries).
+struct SizeOdds {
+  std::array<double, kNumAuto> p{}, base{};
+};
+
+// SizeOdds of every size up to max_rows, per (function, threshold), kept
+// and extended as larger sizes come up.
+std::vector<SizeOdds> false_survivor_odds(uint32_t max_rows, int sim, uint64_t p, uint64_t q) {
   static std::mutex mu;
-  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>,
-                  std::vector<std::array<double, kNumAuto>>> memo;
+  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>, std::vector<SizeOdds>> memo;
   std::lock_guard<std::mutex> lk(mu);
-  std::vector<std::array<double, kNumAuto>> &v = memo[{sim, {p, q}}];
+  std::vector<SizeOdds> &v = memo[{sim, {p, q}}];
   if (v.empty()) v.push_back({});  // size 0: never pairs
   for (uint32_t a = (uint32_t)v.size(); a <= max_rows; ++a) {
     const uint64_t L = 2ull * a;
     const int64_t slack = (int64_t)L - 2 * (int64_t)omin_of(sim, a, a, p, q);
-    std::array<double, kNumAuto> pr{};
+    SizeOdds o;
     for (int k = 0; k < kNumAuto; ++k) {
       const double b = 64.0 * kAutoWords[k];
       const double pi = 0.5 * (1.0 - std::pow(1.0 - 2.0 / b, (double)L));
-      pr[k] = binomial_cdf((int)b, pi, slack);
+      const double P = binomial_cdf((int)b, pi, slack), s = kPairsPerStep[k];
+      const double step_hit = -std::expm1(s * std::log1p(-std::min(P, 1.0 - 1e-16)));
+      o.p[k] = P;
+      o.base[k] = kFilterNsPerPair[k] + step_hit * kSlowEntryNs / s;
     }
-    v.push_back(pr);
+    v.push_back(o);
   }
-  return std::vector<std::array<double, kNumAuto>>(v.begin(), v.begin() + max_rows + 1);
+  return std::vector<SizeOdds>(v.begin(), v.begin() + max_rows + 1);
 }
 
 // A task's rows of one size: their band pairs and their number.
@@ -742,62 +767,70 @@ struct SizeLoad {
 };
 
 // The width classes of a task whose rows of size a are load[a]
-// (a = 0 .. load.size() - 1).
+// (a = 0 .. load.size() - 1).  The dynamic program steps over the sizes that
+// hold rows: a width change at an empty size costs what it costs at the next
+// size with rows.
 std::vector<WidthClass> choose_classes(const std::vector<SizeLoad> &load, int sim, uint64_t p,
-                                       uint64_t q) {
+                                       uint64_t q, double waves) {
   const uint32_t n = std::max<uint32_t>((uint32_t)load.size() - 1, 1);
   const auto odds = false_survivor_odds(n, sim, p, q);
-  // tile shape of each width's kernel, and the waves of a filter grid
+  // tile shape of each width's kernel (waves: the waves of a filter grid)
   double tile_rows[kNumAuto], tile_cols[kNumAuto];
   for (int k = 0; k < kNumAuto; ++k) {
     const uint32_t w = kAutoWords[k];
     tile_rows[k] = std::max<uint32_t>(1, filter_shape(filter_padded_words(w), w < 8).rows);
     tile_cols[k] = kClassTileCols[k];
   }
-  const double waves = (double)filter_grid_blocks() * (kBlock / 64);
-  // best[a][k]: least cost of sizes 1..a with size a at width k
-  std::vector<std::array<double, kNumAuto>> best(n + 1);
-  std::vector<std::array<int8_t, kNumAuto>> from(n + 1);
-  for (uint32_t a = 1; a <= n; ++a) {
+  std::vector<uint32_t> sizes;
+  for (uint32_t a = 1; a <= n; ++a)
+    if (a < load.size() && load[a].rows > 0) sizes.push_back(a);
+  if (sizes.empty()) sizes.push_back(n);
+  // best[i][k]: least cost of the sizes up to sizes[i], sizes[i] at width k
+  std::vector<std::array<double, kNumAuto>> best(sizes.size());
+  std::vector<std::array<int8_t, kNumAuto>> from(sizes.size());
+  for (size_t i = 0; i < sizes.size(); ++i) {
+    const uint32_t a = sizes[i];
     const double w = a < load.size() ? load[a].band : 0.0;
     const double rows = a < load.size() ? load[a].rows : 0.0;
     const double cols = rows > 0 ? w / rows : 0.0;  // band columns of a row
     for (int k = 0; k < kNumAuto; ++k) {
-      const double P = odds[a][k], s = kPairsPerStep[k];
-      const double step_hit = -std::expm1(s * std::log1p(-std::min(P, 1.0 - 1e-16)));
       const double tiles = std::min(waves, std::max(1.0, rows / tile_rows[k]) *
                                                std::max(1.0, std::ceil(cols / tile_cols[k])));
       const double surv = std::max(kSurvivorNs, kSurvivorWaveNs[k] / tiles);
-      const double here = w * (kFilterNsPerPair[k] + step_hit * kSlowEntryNs / s + P * surv);
-      if (a == 1) {
-        best[a][k] = here + kClassLaunchNs[k];
-        from[a][k] = (int8_t)k;
+      const double here = w * (odds[a].base[k] + odds[a].p[k] * surv);
+      if (i == 0) {
+        best[i][k] = here + kClassLaunchNs[k];
+        from[i][k] = (int8_t)k;
         continue;
       }
-      double b = best[a - 1][k];
+      double b = best[i - 1][k];
       int8_t f = (int8_t)k;
       for (int j = 0; j < k; ++j)
-        if (best[a - 1][j] + kClassLaunchNs[k] < b) {
-          b = best[a - 1][j] + kClassLaunchNs[k];
+        if (best[i - 1][j] + kClassLaunchNs[k] < b) {
+          b = best[i - 1][j] + kClassLaunchNs[k];
           f = (int8_t)j;
         }
-      best[a][k] = here + b;
-      from[a][k] = f;
+      best[i][k] = here + b;
+      from[i][k] = f;
     }
   }
+  const size_t last = sizes.size() - 1;
   int k = 0;
   for (int j = 1; j < kNumAuto; ++j)
-    if (best[n][j] < best[n][k]) k = j;
-  std::vector<uint32_t> width(n + 1, kAutoWords[0]);
-  for (uint32_t a = n; a >= 1; --a) {
-    width[a] = kAutoWords[k];
-    k = from[a][k];
+    if (best[last][j] < best[last][k]) k = j;
+  std::vector<uint32_t> width(sizes.size());
+  for (size_t i = sizes.size(); i-- > 0;) {
+    width[i] = kAutoWords[k];
+    k = from[i][k];
   }
+  // a class ends at the last size with rows before the next width; the
+  // last class covers every size up to n
   std::vector<WidthClass> cls;
-  for (uint32_t a = 1; a <= n; ++a) {
-    if (!cls.empty() && cls.back().words == width[a]) cls.back().max_size = a;
-    else cls.push_back({a, width[a]});
+  for (size_t i = 0; i < sizes.size(); ++i) {
+    if (!cls.empty() && cls.back().words == width[i]) cls.back().max_size = sizes[i];
+    else cls.push_back({sizes[i], width[i]});
   }
+  cls.back().max_size = n;
   return cls;
 }
 
@@ -1218,11 +1251,45 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
     td.col_base = (uint32_t)C.h_sides[tk.col_side].base;
     td.self = tk.self ? 1u : 0u;
     td.col_sstart_off = (uint64_t)tk.col_side * C.stride;
-    if (automatic)
+    if (!automatic) classes[k].push_back({a_max, wpad});
+  }
+  if (automatic) {
+    // the tasks' width classes are independent: many tasks are planned on
+    // several host threads, each taking the next task in turn
+    const double waves = (double)filter_grid_blocks() * (kBlock / 64);
+    auto plan_task = [&](uint32_t k) {
+      const TaskIn &tk = tasks[k];
       classes[k] = choose_classes(
           band_by_size(R, C, tk.sim, tk.p, tk.q, tk.row_side, tk.col_side, tk.self), tk.sim,
-          tk.p, tk.q);
-    else classes[k].push_back({a_max, wpad});
+          tk.p, tk.q, waves);
+    };
+    // threads only pay when the sizes to plan are many (a thread's start
+    // costs about what a few thousand sizes do)
+    uint64_t work = 0;
+    for (uint32_t k = 0; k < n_tasks; ++k) work += R.side_max[tasks[k].row_side];
+    const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t n_threads =
+        work < kPlanThreadSizes ? 1u : std::min<uint32_t>({kPlanThreads, hw, n_tasks / 16});
+    if (n_threads <= 1) {
+      for (uint32_t k = 0; k < n_tasks; ++k) plan_task(k);
+    } else {
+      std::atomic<uint32_t> next{0};
+      std::exception_ptr failed;
+      std::mutex fail_mu;
+      auto worker = [&]() {
+        try {
+          for (uint32_t k; (k = next.fetch_add(1)) < n_tasks;) plan_task(k);
+        } catch (...) {
+          std::lock_guard<std::mutex> lk(fail_mu);
+          if (!failed) failed = std::current_exception();
+        }
+      };
+      std::vector<std::thread> pool;
+      for (uint32_t t = 1; t < n_threads; ++t) pool.emplace_back(worker);
+      worker();
+      for (auto &th : pool) th.join();
+      if (failed) std::rethrow_exception(failed);
+    }
   }
   // The cutoff point (Section 3.5) of every task at its widest width: rows
   // of larger sets skip the bitmap filter and take prefix-filtered
@@ -1779,6 +1846,32 @@ float ms_since(std::chrono::steady_clock::time_point t0) {
 
 // ssj_self_join / ssj_rs_join: one task, each side in its own space (the
 // self-join's row and column space are one).
+// A point in a stream the host can wait for without waiting for the work
+// enqueued after it.
+struct Marker {
+  hipEvent_t ev = nullptr;
+  Marker() { check(hipEventCreateWithFlags(&ev, hipEventDisableTiming)); }
+  ~Marker() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  Marker(const Marker &) = delete;
+  Marker &operator=(const Marker &) = delete;
+  void record(hipStream_t st) { check(hipEventRecord(ev, st)); }
+  void wait() { check(hipEventSynchronize(ev)); }
+};
+
+// In automatic mode the bitmaps up to the cascade width (one build pass,
+// the narrower widths folded from it) do not depend on the plan: they are
+// enqueued before the host waits for the group starts, so that the device
+// builds them while the host plans.
+void early_bitmaps(Space &sp, const JoinConfig &jc, Arena &ar, JoinCounters *ctr,
+                   hipStream_t st) {
+  if (jc.b_bits != 0 || jc.survivors_only || !sp.rank) return;
+  static constexpr uint32_t words[4] = {1, 2, 4, kCascadeWords}, bits[4] = {64, 128, 256, 512};
+  static_assert(kCascadeWords == 8, "the cascade width is the widest of one fold pass");
+  space_bitmaps_multi(sp, words, bits, 4, ar, ctr, st);
+}
+
 int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint64_t *s_bm,
              bool self, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
              const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
@@ -1802,7 +1895,11 @@ int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const u
     sync(st);
     space_sort(A, r_bm == nullptr, ar, ar, st);
     if (!self) space_sort(B, s_bm == nullptr, ar, ar, st);
-    sync(st);
+    Marker sorted;
+    sorted.record(st);
+    early_bitmaps(A, jc, ar, ctr, st);
+    if (!self) early_bitmaps(B, jc, ar, ctr, st);
+    sorted.wait();
     space_finish(A);
     if (!self) space_finish(B);
     Space &C = self ? A : B;
@@ -1909,7 +2006,10 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
     space_begin(A, sides.data(), n, ar, st);
     sync(st);
     space_sort(A, true, ar, ar, st);
-    sync(st);
+    Marker sorted;
+    sorted.record(st);
+    early_bitmaps(A, jc, ar, ctr, st);
+    sorted.wait();
     space_finish(A);
     run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
