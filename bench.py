@@ -48,8 +48,8 @@ DTYPE_INT = "u32"
 # sources they were taken with: any change to them makes the figure null
 # until the counters are taken again.  The summary and commands are in
 # profiles/.
-TRAFFIC = {"sources_sha256": "6bd1fdd94e49e52ded8225f3581056f69672d1cd91d2b894f656a8cbb942f558",
-           "fetch_kib": 89106.6, "write_kib": 20665.8,
+TRAFFIC = {"sources_sha256": "f685db314776c0a5e6c80308e2a6e5cff8a9a616846c39931d23adde248f9ccd",
+           "fetch_kib": 93691.5, "write_kib": 14714.8,
            "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
