@@ -6,6 +6,12 @@ filter over the length band, exact verification, sorting and copying the pairs
 to host memory.  The metric is
 length-band pairs per second of wall time (pairs the join accounts for, the
 paper's GPU algorithm evaluates every one of them with the bitmap filter).
+After the timed joins the default run adds, in the same line: the prepared
+join's graph replay, the pair list's parity against the oracle's stored list,
+the CPU oracle's rate on a row sample, the served form's p50/p99 latency
+(query batches against a resident 5,000,000-set index under continuous
+batching), and the batched form (256 uneven instances in one call against one
+call each).
 
 Other modes (not the default):
   --mode batch   256 uneven self-join instances: one ssj_self_join_batch call
@@ -120,6 +126,8 @@ def main():
                     help="serve mode: sets in the resident index")
     ap.add_argument("--slots", type=int, default=2,
                     help="served form: calls in flight at once (continuous batching)")
+    ap.add_argument("--batch-instances-default", type=int, default=256,
+                    help="default mode: instances of the batched leg (0 disables it)")
     ap.add_argument("--serve-batches-default", type=int, default=300,
                     help="default mode: measured query batches of the served leg "
                          "(0 = no served leg)")
@@ -268,7 +276,59 @@ def main():
         line["served_vs_plain"] = {"p50": head["p50_plain_over_continuous"],
                                    "p99": head["p99_plain_over_continuous"]}
         line["served"] = sv
+    if args.batch_instances_default:
+        # the batched form: one call for many uneven instances against one
+        # call per instance, and the prepared call replayed from a graph
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(args.batch_instances_default)
     print(json.dumps(line), flush=True)
+
+
+def batched_leg(n_instances, steps=3):
+    """ssj_self_join_batch over the first ``n_instances`` batched instances
+    (automatic widths) against the same instances one ssj_self_join call
+    each, and the prepared call's replay; pairs must agree."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1711_07295_amd as ssj
+
+    t0 = time.perf_counter()
+    inst = gen.batched_instances(n_instances)
+    log(f"batched leg: generated {len(inst)} instances in {time.perf_counter() - t0:.1f} s")
+    devs = [ssj.to_device(c.offsets, c.tokens) for c, _ in inst]
+    ps, qs = [t[0] for _, t in inst], [t[1] for _, t in inst]
+    torch.cuda.synchronize()
+    got, st = ssj.ssj_self_join_batch(devs, ps, qs)  # warm-up
+    times = []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        got, st = ssj.ssj_self_join_batch(devs, ps, qs)
+        times.append(time.perf_counter() - t1)
+    t1 = time.perf_counter()
+    seq = [ssj.ssj_self_join(d, p, q, b_bits=0)[0] for d, p, q in zip(devs, ps, qs)]
+    seq_ms = (time.perf_counter() - t1) * 1e3
+    same = all(np.array_equal(a, b) for a, b in zip(got, seq))
+    plan = ssj.Plan(devs, ps, qs)
+    plan.execute()
+    rt = []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        again, _ = plan.execute()
+        rt.append(time.perf_counter() - t1)
+    plan.close()
+    same = same and all(np.array_equal(a, b) for a, b in zip(got, again))
+    ms = statistics.median(times) * 1e3
+    out = {"workload": f"batched-{len(inst)}", "instances": len(inst),
+           "n_sets": int(sum(c.n_sets for c, _ in inst)), "band_pairs": st["band_pairs"],
+           "results": st["results"], "ms_per_call": ms, "pairs_per_s": st["band_pairs"] / (ms / 1e3),
+           "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms,
+           "graph_replay_ms": statistics.median(rt) * 1e3,
+           "graph_speedup_vs_sequential": seq_ms / (statistics.median(rt) * 1e3),
+           "same_pairs": same}
+    log(f"batched leg: {out}")
+    return out
 
 
 def golden_parity(workload, checksum, sim, p, q, pairs):
