@@ -178,6 +178,9 @@ __device__ __forceinline__ uint32_t wide_distance(const uint64_t *__restrict__ x
 // true pair would hold its whole round that long.
 constexpr uint32_t kLongMerge = 128;
 
+// Result keys a verification wave stages in LDS.
+constexpr uint32_t kWaveResults = 256;
+
 struct VerifyArgs {
   VerifySpace rows, cols;
   const uint32_t *side_task;
@@ -314,8 +317,17 @@ __global__ __launch_bounds__(kBlock) void k_verify(const uint2 *__restrict__ que
                                                    unsigned long long results_cap,
                                                    JoinCounters *__restrict__ ctr) {
   __shared__ uint2 pend[kBlock / 64][128];
+  // result keys, staged per wave and written with one reservation per
+  // workgroup at the end (or per wave when a wave's list fills): one
+  // same-address atomic per workgroup instead of one per round
+  __shared__ unsigned long long rkeys[kBlock / 64][kWaveResults];
+  __shared__ unsigned long long rbase[kBlock / 64];
+  __shared__ uint32_t block_surv;
   uint2 *buf = pend[threadIdx.x >> 6];
+  unsigned long long *rk = rkeys[threadIdx.x >> 6];
+  uint32_t rfill = 0;
   const uint32_t lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) block_surv = 0;
   unsigned long long count = ctr->queue_count;
   if (count > cap) count = cap;
   const unsigned long long windows = (count + 63) / 64;
@@ -339,13 +351,20 @@ __global__ __launch_bounds__(kBlock) void k_verify(const uint2 *__restrict__ que
     }
     const unsigned long long m = __ballot(hit);
     if (m) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&ctr->results, (unsigned long long)__popcll(m));
-      base = __shfl(base, 0, 64);
-      if (hit) {
-        const unsigned long long pos = base + (unsigned long long)__popcll(m & __lanemask_lt());
-        if (pos < results_cap) results[pos] = key;
+      const uint32_t n = (uint32_t)__popcll(m);
+      if (rfill + n > kWaveResults) {
+        // this wave's list is full: write it out on its own
+        __builtin_amdgcn_wave_barrier();
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&ctr->results, (unsigned long long)rfill);
+        base = __shfl(base, 0, 64);
+        for (uint32_t x = lane; x < rfill; x += 64)
+          if (base + x < results_cap) results[base + x] = rk[x];
+        __builtin_amdgcn_wave_barrier();
+        rfill = 0;
       }
+      if (hit) rk[rfill + (uint32_t)__popcll(m & __lanemask_lt())] = key;
+      rfill += n;
     }
   };
   // the next window's entry is loaded before the current one is used
@@ -378,16 +397,32 @@ __global__ __launch_bounds__(kBlock) void k_verify(const uint2 *__restrict__ que
     surv += lane < fill ? 1u : 0u;
     round(mine, lane < fill);
   }
-  // survivors seen, one atomic per workgroup (same-address atomics from
-  // every XCD are served one at a time)
-  __shared__ uint32_t block_surv;
-  if (threadIdx.x == 0) block_surv = 0;
-  __syncthreads();
+  // survivors seen and the staged results: one atomic each per workgroup
+  // (same-address atomics from every XCD are served one at a time)
+  const uint32_t wv = threadIdx.x >> 6;
   uint32_t s = surv;
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-  if (lane == 0 && s) atomicAdd(&block_surv, s);
+  __syncthreads();  // block_surv was cleared at the start
+  if (lane == 0) {
+    if (s) atomicAdd(&block_surv, s);
+    rbase[wv] = rfill;
+  }
   __syncthreads();
-  if (threadIdx.x == 0 && block_surv) atomicAdd(&ctr->survivors, (unsigned long long)block_surv);
+  if (threadIdx.x == 0) {
+    if (block_surv) atomicAdd(&ctr->survivors, (unsigned long long)block_surv);
+    unsigned long long total = 0;
+    for (uint32_t k = 0; k < kBlock / 64; ++k) total += rbase[k];
+    unsigned long long at = total ? atomicAdd(&ctr->results, total) : 0ull;
+    for (uint32_t k = 0; k < kBlock / 64; ++k) {
+      const unsigned long long nk = rbase[k];
+      rbase[k] = at;
+      at += nk;
+    }
+  }
+  __syncthreads();
+  const unsigned long long base = rbase[wv];
+  for (uint32_t x = lane; x < rfill; x += 64)
+    if (base + x < results_cap) results[base + x] = rk[x];
 }
 
 // The deferred long pairs (their bitmap tests passed).  A few of them (up to

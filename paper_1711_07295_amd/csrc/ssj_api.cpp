@@ -1505,11 +1505,11 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   // its tile never resumed.  Chunks are small against the queue, so that
   // many waves hold one in a round.  The unused end of a chunk costs
   // verification a sentinel read per slot, a reservation costs an atomic on
-  // one address.  The width classes below the widest automatic width keep
-  // false survivors rare (their widths are chosen for it), so their waves
-  // take kFilterStage slots at a time; the widest class (every size beyond
-  // the others, where the bits saturate) and a fixed width can keep many
-  // pairs, and their waves take up to 1024.
+  // one address.  The width classes below the cascade width keep false
+  // survivors rare (their widths are chosen for it), so their waves take
+  // kFilterStage slots at a time; the widest class (every size beyond the
+  // others, where the bits saturate) and a fixed width can keep many pairs,
+  // and their waves take up to 1024.
   static_assert(kFilterStage <= 4096, "the queue holds at least 4096 entries");
   uint64_t qcap = std::max<uint64_t>(4096, std::min<uint64_t>(jc.cap, pl.band_pairs + 1));
   uint32_t dense_chunk =
