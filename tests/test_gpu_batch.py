@@ -46,6 +46,24 @@ def test_batch_matches_oracle_per_instance(b):
     assert st["results"] == sum(len(g) for g in got)
 
 
+def test_many_tasks_with_large_sets_match_the_oracle():
+    """48 instances whose largest sets reach 2000 tokens: the library plans
+    their width classes on several host threads (the tasks' largest sizes
+    sum past its threshold); each instance's pairs equal the oracle's, on
+    a repeat of the call too."""
+    cols = [_col(900 + k, 120 + 7 * k, universe=20000, hi=2000, median=300.0, planted=0.3, lo=2)
+            for k in range(48)]
+    pq = [[(1, 2), (7, 10), (4, 5), (9, 10)][k % 4] for k in range(48)]
+    devs = [_dev(c) for c in cols]
+    assert sum(int(c.sizes().max()) for c in cols) >= 65536
+    want = [oracle.self_join(c.offsets, c.tokens, p, q) for c, (p, q) in zip(cols, pq)]
+    for _ in range(2):
+        got, st = ssj.ssj_self_join_batch(devs, [p for p, _ in pq], [q for _, q in pq])
+        for g, w, c, t in zip(got, want, cols, pq):
+            assert np.array_equal(g, w), (c.n_sets, t, len(g), len(w))
+        assert st["results"] == sum(len(w) for w in want)
+
+
 def test_batch_equals_single_calls_and_resumes_after_overflow():
     cols = [_col(700 + k, n, universe=300, planted=0.3) for k, n in enumerate((3000, 800, 5000))]
     pq = [(1, 2), (1, 2), (3, 5)]

@@ -12,6 +12,10 @@ full_golden.json holds the input checksums and the SHA-256 of every list).
                 every pair the library reports passes the oracle's
                 predicate
 
+  served-5m     the smallest query batches of the served form that hold a
+                perturbed copy, against the 5,000,000-set index, against
+                the oracle's R-S join over each batch's length band
+
 A fixed b = 64 at t = 1/2 is left out: about a tenth of the 2.4e11 band
 pairs survive a 64-bit bitmap at that threshold, and the test would spend
 minutes draining the survivor queue; the automatic widths cover that
@@ -114,3 +118,52 @@ def test_selfjoin_10m_row_sample(c10m, b, pq):
     want = lists[pq]
     assert np.array_equal(mine, want), (b, pq, len(mine), len(want))
     assert st["results"] == len(got)
+
+
+@pytest.fixture(scope="module")
+def served5m():
+    sw = gen.served_workload(60)  # the served form's 5,000,000-set index
+    res = sw.resident
+    idx = ssj.Index(ssj.to_device(res.offsets, res.tokens))
+    yield sw, idx
+    idx.close()
+
+
+def _band_subset(res, r_sizes, p, q):
+    """The resident sets a batch of sizes r_sizes can pair with (Table 2's
+    length filter, the oracle's predicate): their indices and a CSR copy."""
+    sizes = np.diff(res.offsets).astype(np.int64)
+    ok = np.zeros(int(sizes.max()) + 1, dtype=bool)
+    for c in np.unique(sizes):
+        ok[c] = any(oracle.length_ok(oracle.JACCARD, int(a), int(c), p, q)
+                    for a in np.unique(r_sizes))
+    keep = np.nonzero(ok[sizes])[0]
+    n = sizes[keep]
+    off = np.zeros(keep.shape[0] + 1, dtype=np.uint64)
+    np.cumsum(n, out=off[1:])
+    starts = res.offsets[:-1][keep].astype(np.int64)
+    gather = np.repeat(starts - off[:-1].astype(np.int64), n) + np.arange(int(off[-1]))
+    return keep, off, res.tokens[gather]
+
+
+def test_served_batches_against_the_5m_index_match_the_oracle(served5m):
+    """The four smallest query batches of the served workload that hold a
+    perturbed copy of a resident set, against the real 5,000,000-set index
+    in one call: pairs element by element equal to
+    the oracle's R-S join (Eq. 1) over the resident sets inside each batch's
+    length band (sets outside it cannot reach the threshold, Table 2)."""
+    sw, idx = served5m
+    by_size = np.argsort([b.n_sets for b in sw.batches], kind="stable")
+    order = [k for k in by_size if sw.copies[k].any()][:4]  # each holds a perturbed copy
+    batches = [sw.batches[k] for k in order]
+    ps, qs = [sw.thresholds[k][0] for k in order], [sw.thresholds[k][1] for k in order]
+    got, st = idx.query([ssj.to_device(b.offsets, b.tokens) for b in batches], ps, qs)
+    found = 0
+    for b, p, q, g in zip(batches, ps, qs, got):
+        keep, off, tok = _band_subset(sw.resident, b.sizes(), p, q)
+        w = oracle.rs_join(b.offsets, b.tokens, off, tok, p, q)
+        want = np.stack([w[:, 0], keep[w[:, 1]].astype(np.uint32)], axis=1) if len(w) else w
+        assert np.array_equal(g, want), (b.n_sets, p, q, len(g), len(want))
+        found += len(want)
+    assert found > 0  # the perturbed copies find their sources
+    assert st["results"] == found
