@@ -3,7 +3,8 @@
 // final ordering of the result pairs.
 //
 // Per pass: (1) every workgroup counts the digits of its kTile keys,
-// (2) the digit-major table of counts is scanned, (3) every workgroup
+// (2) the digit-major table of counts is scanned (by the scatter itself
+// when there are few workgroups), (3) every workgroup
 // ranks its keys stably -- wave by wave, 64 keys at a time, peers with
 // the same digit found by eight ballots -- and scatters them.
 #include "ssj_internal.h"
@@ -17,6 +18,8 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kWaveKeys = kTile / kWaves; // contiguous keys per wave
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
+// Sort blocks up to which a pass's scatter sums the digit counts itself.
+constexpr uint64_t kFoldBlocks = 64;
 
 __device__ __forceinline__ uint32_t digit_of(unsigned long long k, int shift) {
   return (uint32_t)(k >> shift) & 0xFFu;
@@ -44,6 +47,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const unsigned long long 
   }
 }
 
+// FOLD (few sort blocks): hist holds the blocks' raw digit counts, and each
+// block sums its digit's row itself (its offset and the digit's total), so
+// that a pass needs no scan launch; otherwise hist holds the scanned counts
+// and totals the digit totals (k_radix_digit_scan).
+template <bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const unsigned long long *__restrict__ keys, unsigned long long *__restrict__ out, uint64_t n,
     int shift, uint32_t nblocks, const uint32_t *__restrict__ hist_scanned,
@@ -59,7 +67,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
   {
     __shared__ uint32_t wtot[kWaves];
     const int d = threadIdx.x;  // kBlock == 256 digits
-    const uint32_t tot = totals[d];
+    uint32_t tot = 0, mine = 0;
+    if (FOLD) {
+      const uint32_t *__restrict__ row = hist_scanned + (uint64_t)d * nblocks;
+      for (uint32_t b = 0; b < nblocks; ++b) {
+        const uint32_t v = row[b];
+        mine += b < blockIdx.x ? v : 0u;
+        tot += v;
+      }
+    } else {
+      tot = totals[d];
+      mine = hist_scanned[(uint64_t)d * nblocks + blockIdx.x];
+    }
     uint32_t inc = tot;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -70,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     __syncthreads();
     uint32_t pre = 0;
     for (int v = 0; v < w; ++v) pre += wtot[v];
-    gbase[d] = pre + inc - tot + hist_scanned[(uint64_t)d * nblocks + blockIdx.x];
+    gbase[d] = pre + inc - tot + mine;
   }
   __syncthreads();
 
@@ -186,10 +205,15 @@ hipError_t radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uin
   for (int p = 0; p < n_shifts; ++p) {
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, st, src, n, shifts[p],
                        (uint32_t)nb, hist);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kBlock), 0, st, hist, (uint32_t)nb,
-                       totals);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, st, src, dst, n,
-                       shifts[p], (uint32_t)nb, hist, totals);
+    if (nb <= kFoldBlocks) {
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, src,
+                         dst, n, shifts[p], (uint32_t)nb, hist, totals);
+    } else {
+      hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kBlock), 0, st, hist, (uint32_t)nb,
+                         totals);
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, src,
+                         dst, n, shifts[p], (uint32_t)nb, hist, totals);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     unsigned long long *t = src;
