@@ -52,9 +52,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "autotune_table.h")
 WIDTHS = (64, 128, 256, 512, 1024, 2048)
 # pairs of one step of the filter kernel at each width: the matrix-core
-# kernel scores 32 columns against 32 * RT rows (RT = 4 at 64 bits, 3 at 128
+# kernel scores 32 columns against 32 * RT rows (RT = 6 at 64 bits, 3 at 128
 # and 256), the vector-ALU kernel 64 * R rows against U columns
-PAIRS_PER_STEP = {64: 4096, 128: 3072, 256: 3072, 512: 64, 1024: 64, 2048: 64}
+PAIRS_PER_STEP = {64: 6144, 128: 3072, 256: 3072, 512: 64, 1024: 64, 2048: 64}
 TILE_COLS = (1024, 2048, 4096)
 P, Q = 4, 5
 

@@ -14,11 +14,11 @@
 #include <cstdint>
 
 namespace ssj {
-constexpr double kFilterNsPerPair[6] = {3.0920e-05, 4.8516e-05, 1.1137e-04, 8.5293e-04, 2.0178e-03, 5.7975e-03};
-constexpr double kSlowEntryNs = 4.4148e+00;
-constexpr double kSurvivorNs = 7.6805e-02;
-constexpr double kSurvivorWaveNs[6] = {4.5511e+00, 4.5986e+00, 4.6424e+00, 5.6521e+00, 6.9843e+00, 1.6969e+01};
-constexpr double kPairsPerStep[6] = {4096.0, 3072.0, 3072.0, 64.0, 64.0, 64.0};
-constexpr double kClassLaunchNs[6] = {3.2556e+04, 3.1516e+04, 4.1235e+04, 3.6036e+04, 4.2674e+04, 7.2831e+04};
+constexpr double kFilterNsPerPair[6] = {2.9672e-05, 4.8339e-05, 1.1220e-04, 8.5153e-04, 2.0138e-03, 5.7949e-03};
+constexpr double kSlowEntryNs = 3.7727e+00;
+constexpr double kSurvivorNs = 7.7342e-02;
+constexpr double kSurvivorWaveNs[6] = {4.6449e+00, 4.5711e+00, 4.6161e+00, 5.6737e+00, 6.9138e+00, 1.7046e+01};
+constexpr double kPairsPerStep[6] = {6144.0, 3072.0, 3072.0, 64.0, 64.0, 64.0};
+constexpr double kClassLaunchNs[6] = {4.0354e+04, 3.1596e+04, 4.0835e+04, 3.5796e+04, 4.2994e+04, 7.3710e+04};
 constexpr uint32_t kClassTileCols[6] = {4096, 4096, 4096, 2048, 1024, 2048};
 }  // namespace ssj

@@ -937,12 +937,14 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
   X(48, 1, 1)                \
   X(64, 1, 1)
 
-// Matrix-core kernels: (words, row tiles of 32 per wave)
+// Matrix-core kernels: (words, row tiles of 32 per wave).  At b = 64 six row
+// tiles (three waves per SIMD) beat four (four waves per SIMD): a column
+// step's loads, loop control and tests serve six products instead of four.
 // (b = 512 stays on the vector ALUs: with eight 64-bit blocks per column a
 // step streams 8 bytes of column planes per pair at the row-tile counts the
 // registers allow, more than L2 delivers; the vector-ALU kernel is faster.)
 #define SSJ_MFMA_SHAPES(X) \
-  X(1, 4)                  \
+  X(1, 6)                  \
   X(2, 3)                  \
   X(4, 3)
 
