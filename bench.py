@@ -54,8 +54,8 @@ DTYPE_INT = "u32"
 # sources they were taken with: any change to them makes the figure null
 # until the counters are taken again.  The summary and commands are in
 # profiles/.
-TRAFFIC = {"sources_sha256": "f685db314776c0a5e6c80308e2a6e5cff8a9a616846c39931d23adde248f9ccd",
-           "fetch_kib": 93691.5, "write_kib": 14714.8,
+TRAFFIC = {"sources_sha256": "33c692babba3af6b3db4026d22911a61033b87334aae5ba76cb79b40ed02720c",
+           "fetch_kib": 67641.8, "write_kib": 11376.4,
            "fetch_factor": 1.9999, "write_factor": 1.0000}
 
 
