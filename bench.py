@@ -128,7 +128,7 @@ def main():
                     help="served form: calls in flight at once (continuous batching)")
     ap.add_argument("--batch-instances-default", type=int, default=256,
                     help="default mode: instances of the batched leg (0 disables it)")
-    ap.add_argument("--serve-batches-default", type=int, default=300,
+    ap.add_argument("--serve-batches-default", type=int, default=1000,
                     help="default mode: measured query batches of the served leg "
                          "(0 = no served leg)")
     ap.add_argument("--steps", type=int, default=10)

@@ -177,6 +177,83 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
   if (__ballot(unsorted) && (threadIdx.x & 63) == 0) atomicOr(&ctr->error, kErrUnsorted);
 }
 
+// Bitmap-Xor bitmaps at 16 or 32 words (and the narrower widths of `fold`)
+// of only the sets whose size lies in their side's window: the wide width
+// classes are read by few sets, whose tokens are a fraction of the
+// collection's.  A workgroup takes the segment of kSegSets sets in caller
+// order that the segmented build takes, lists the sets of the segment that
+// fall in the window, and its waves take the listed sets one at a time:
+// the lanes stride over the set's tokens (these sets are long), flip their
+// bits in the wave's LDS bitmap and write it to the set's size-order row.
+// The token order is not checked here: a full build of the same sets does.
+template <int WO>
+__global__ __launch_bounds__(kBlock) void k_build_bitmaps_window(
+    const SideDesc *__restrict__ sides, uint32_t n_sides, const uint32_t *__restrict__ rank,
+    const SizeWindow *__restrict__ win, uint64_t n, uint64_t *__restrict__ out, FoldOut fold) {
+  __shared__ uint32_t listed[kSegSets];
+  __shared__ uint32_t n_listed;
+  __shared__ uint32_t lbits[kWavesPerBlock][2 * WO];
+  const uint32_t sid = side_of_block(sides, n_sides, blockIdx.x);
+  const SideDesc sd = sides[sid];
+  const uint64_t seg0 = (uint64_t)(blockIdx.x - sd.blk0) * kSegSets;
+  const SizeWindow w = win[sid];
+  if (seg0 >= sd.n || w.lo > w.hi) return;  // whole workgroup leaves together
+  const uint32_t nseg = (uint32_t)min((uint64_t)kSegSets, sd.n - seg0);
+  const uint64_t *__restrict__ offsets = sd.offsets;
+  const uint32_t *__restrict__ tokens = sd.tokens;
+  if (threadIdx.x == 0) n_listed = 0;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nseg; i += kBlock) {
+    const uint64_t size = offsets[seg0 + i + 1] - offsets[seg0 + i];
+    if (size >= w.lo && size <= w.hi) listed[atomicAdd(&n_listed, 1u)] = i;
+  }
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6, count = n_listed;
+  uint32_t *bits = lbits[wv];
+  constexpr uint32_t kMask = 64 * WO - 1;
+  for (uint32_t e = wv; e < count; e += kWavesPerBlock) {
+    const uint32_t x = listed[e];
+    for (uint32_t i = lane; i < 2 * WO; i += 64) bits[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t o0 = offsets[seg0 + x], o1 = offsets[seg0 + x + 1];
+    // four loads in flight per lane before their bits are flipped
+    for (uint64_t t = o0 + lane; t < o1; t += 256) {
+      uint32_t v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = t + 64 * k < o1 ? tokens[t + 64 * k] : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (t + 64 * k < o1) atomicXor(&bits[(v[k] & kMask) >> 5], 1u << (v[k] & 31));
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t row = rank[sd.base + seg0 + x];
+    if (row < n) {
+      if (lane < (uint32_t)WO)
+        out[row * WO + lane] = (uint64_t)bits[2 * lane] | ((uint64_t)bits[2 * lane + 1] << 32);
+      // narrower widths b / 2^(f+1): word i combines words i + m (b'/64)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const uint32_t wf = (uint32_t)WO >> (f + 1);
+        if (wf == 0 || fold.out[f] == nullptr || lane >= wf) continue;
+        uint64_t v = 0;
+        for (uint32_t m = 0; m < (uint32_t)WO / wf; ++m) {
+          const uint32_t src = lane + m * wf;
+          v ^= (uint64_t)bits[2 * src] | ((uint64_t)bits[2 * src + 1] << 32);
+        }
+        fold.out[f][row * wf + lane] = v;
+      }
+    }
+    // every lane has read the bitmap before the next set clears it
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_sorted(const uint64_t *__restrict__ offsets,
                                                          const uint32_t *__restrict__ tokens,
                                                          uint64_t n, JoinCounters *__restrict__ ctr) {
@@ -272,6 +349,58 @@ __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restr
   planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
 }
 
+// The wide ranges of every side from its group starts, on the device (one
+// workgroup): side s holds the sets from its first position of size above
+// kWideMin to its end, at slots after those of the sides before it; a side
+// with none gets an empty range, wide_lo ~0u and the slot the next side
+// starts at.
+__global__ __launch_bounds__(kBlock) void k_wide_ranges(const SideDesc *__restrict__ sides,
+                                                         uint32_t n_sides,
+                                                         const uint32_t *__restrict__ sstart,
+                                                         uint32_t stride, uint32_t max_size,
+                                                         WideRange *__restrict__ ranges,
+                                                         uint32_t *__restrict__ wide_lo,
+                                                         uint32_t *__restrict__ wide_slot) {
+  __shared__ uint32_t count[kBlock];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t s0 = 0; s0 < n_sides; s0 += kBlock) {
+    const uint32_t s = s0 + threadIdx.x;
+    uint32_t first = 0, n = 0;
+    if (s < n_sides) {
+      n = sides[s].n;
+      first = kWideMin + 1 <= max_size ? sstart[(uint64_t)s * stride + kWideMin + 1] : n;
+      first = min(first, n);
+    }
+    count[threadIdx.x] = n - first;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // exclusive scan of the chunk's counts, after the sides before it
+      uint32_t run = carry;
+      for (uint32_t i = 0; i < kBlock; ++i) {
+        const uint32_t c = count[i];
+        count[i] = run;
+        run += c;
+      }
+      carry = run;
+    }
+    __syncthreads();
+    if (s < n_sides) {
+      const uint32_t base = (uint32_t)sides[s].base, slot = count[threadIdx.x];
+      WideRange r;
+      r.lo = base + first;
+      r.hi = base + n;
+      r.slot = slot;
+      r.side = s;
+      ranges[s] = r;
+      wide_lo[s] = first < n ? base + first : 0xFFFFFFFFu;
+      wide_slot[s] = slot;
+    }
+    __syncthreads();  // count is rewritten by the next chunk
+  }
+}
+
 // Wide Bitmap-Xor bitmaps of the sets in the wide ranges: one wave per set,
 // built in LDS (4096 bits per wave) and written out whole.
 __global__ __launch_bounds__(kBlock) void k_build_wide(const SideDesc *__restrict__ sides,
@@ -346,6 +475,29 @@ hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_
   }
 }
 
+hipError_t launch_build_bitmaps_window(const SideDesc *sides, uint32_t n_sides,
+                                       uint32_t seg_blocks, uint64_t n_total,
+                                       const uint32_t *rank, const SizeWindow *win,
+                                       uint32_t out_words, uint64_t *out, const FoldOut *fold,
+                                       hipStream_t st) {
+  if (n_total == 0 || seg_blocks == 0) return hipSuccess;
+  if (!rank || !win || !out) return hipErrorInvalidValue;
+  const FoldOut f = fold ? *fold : FoldOut{};
+  switch (out_words) {
+    case 16:
+      hipLaunchKernelGGL(k_build_bitmaps_window<16>, dim3(seg_blocks), dim3(kBlock), 0, st, sides,
+                         n_sides, rank, win, n_total, out, f);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_build_bitmaps_window<32>, dim3(seg_blocks), dim3(kBlock), 0, st, sides,
+                         n_sides, rank, win, n_total, out, f);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_check_sorted(const uint64_t *offsets, const uint32_t *tokens, uint64_t n,
                                JoinCounters *ctr, hipStream_t st) {
   if (n == 0) return hipSuccess;
@@ -371,6 +523,15 @@ hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, u
   const uint64_t total = (n + kSignPad) * words * 2;
   hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, st, bm, words, n, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_ranges(const SideDesc *sides, uint32_t n_sides, const uint32_t *sstart,
+                              uint32_t stride, uint32_t max_size, WideRange *ranges,
+                              uint32_t *wide_lo, uint32_t *wide_slot, hipStream_t st) {
+  if (n_sides == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wide_ranges, dim3(1), dim3(kBlock), 0, st, sides, n_sides, sstart, stride,
+                     max_size, ranges, wide_lo, wide_slot);
   return hipGetLastError();
 }
 

@@ -367,6 +367,8 @@ struct Space {
   JoinCounters ctr_h{};
   // bitmaps in size order, one array per width
   uint32_t n_bm = 0;
+  // a build of every set (which checks the token order) is enqueued
+  bool checked = false;
   uint32_t bm_words[kMaxClasses] = {};
   uint64_t *bm[kMaxClasses] = {};
   // sign planes of the bitmaps (matrix-core filter), beside bm[k]
@@ -488,6 +490,7 @@ void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCoun
   sp.bm_words[sp.n_bm] = words;
   sp.bm[sp.n_bm] = out;
   ++sp.n_bm;
+  sp.checked = true;
 }
 
 // Sign planes of the space's bitmaps at `words` words (built before).
@@ -506,40 +509,29 @@ void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st, Launcher 
 }
 
 // Wide bitmaps of every set larger than kWideMin: in size order they are a
-// suffix of each side (from its group start at kWideMin + 1).
+// suffix of each side (from its group start at kWideMin + 1).  The host
+// only sizes the array; the ranges are made on the device from the group
+// starts, so that nothing is copied up (a copy from pageable memory could
+// wait for the work already queued).
 void space_wide(Space &sp, Arena &ar, hipStream_t st, Launcher *L = nullptr) {
   if (sp.wide_built) return;
   sp.wide_built = true;
-  std::vector<uint32_t> lo(sp.n_sides, 0xFFFFFFFFu), slot(sp.n_sides, 0);
-  std::vector<WideRange> ranges;
   uint64_t total = 0;
-  if ((uint64_t)kWideMin + 1 <= (uint64_t)sp.max_size) {
+  if ((uint64_t)kWideMin + 1 <= (uint64_t)sp.max_size)
     for (uint32_t s = 0; s < sp.n_sides; ++s) {
-      const SideDesc &d = sp.h_sides[s];
-      const uint32_t first = sp.ss(s)[kWideMin + 1];
-      if (first >= d.n) continue;
-      WideRange r{};
-      r.lo = (uint32_t)d.base + first;
-      r.hi = (uint32_t)d.base + d.n;
-      r.slot = (uint32_t)total;
-      r.side = s;
-      lo[s] = r.lo;
-      slot[s] = r.slot;
-      total += r.hi - r.lo;
-      if (total >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
-      ranges.push_back(r);
+      const uint32_t n = sp.h_sides[s].n, first = std::min(sp.ss(s)[kWideMin + 1], n);
+      total += n - first;
     }
-  }
   if (total == 0) return;
+  if (total >= 0xFFFFFFFFull) throw Fail{SSJ_E_UNSUPPORTED};
   sp.wide_lo = ar.alloc<uint32_t>(2 * (uint64_t)sp.n_sides);
   sp.wide_slot = sp.wide_lo + sp.n_sides;
-  h2d(sp.wide_lo, lo.data(), sp.n_sides, st);
-  h2d(sp.wide_slot, slot.data(), sp.n_sides, st);
-  WideRange *d_ranges = ar.alloc<WideRange>(ranges.size());
-  h2d(d_ranges, ranges.data(), ranges.size(), st);
+  WideRange *d_ranges = ar.alloc<WideRange>(sp.n_sides);
+  check(launch_wide_ranges(sp.d_sides, sp.n_sides, sp.sstart, sp.stride, sp.max_size, d_ranges,
+                           sp.wide_lo, sp.wide_slot, st));
   sp.bmw = ar.alloc<uint64_t>(total * kWideWords);
   const SideDesc *sides = sp.d_sides;
-  const uint32_t *perm = sp.perm, n_ranges = (uint32_t)ranges.size();
+  const uint32_t *perm = sp.perm, n_ranges = sp.n_sides;
   uint64_t *bmw = sp.bmw;
   go(L, st, [=](hipStream_t s) {
     return launch_build_wide(sides, perm, d_ranges, n_ranges, total, bmw, s);
@@ -594,6 +586,47 @@ void space_bitmaps_multi(Space &sp, const uint32_t *words, const uint32_t *bits,
     return launch_build_bitmaps(sides, n_sides, seg, nn, perm, rank, side_of, 64 * wmax,
                                 SSJ_BM_XOR, wmax, widest, ctr, s, &f);
   });
+  sp.checked = true;
+}
+
+// Bitmap-Xor bitmaps at the power-of-two widths `words` (more than
+// kCascadeWords, at most kMaxFoldWords words) of only the sets whose size
+// lies in their side's window, in one pass: the widest is built and the
+// others folded from it.  The arrays span the space; rows of the other sets
+// stay unwritten, so only the sets inside the windows may be read.  Needs a
+// build of every set enqueued before (it checks the token order).
+void space_bitmaps_window(Space &sp, const uint32_t *words, uint32_t n,
+                          const std::vector<SizeWindow> &win, Arena &ar, hipStream_t st,
+                          Launcher *L) {
+  if (!sp.checked || !sp.rank || win.size() != sp.n_sides || sp.n_bm + n > kMaxClasses)
+    throw Fail{SSJ_E_DEVICE};
+  uint32_t wmax = 0;
+  for (uint32_t k = 0; k < n; ++k) wmax = std::max(wmax, words[k]);
+  FoldOut fold{};
+  uint64_t *widest = ar.alloc<uint64_t>(sp.n * wmax);
+  for (uint32_t k = 0; k < n; ++k) {
+    uint64_t *dst = widest;
+    if (words[k] != wmax) {
+      dst = ar.alloc<uint64_t>(sp.n * words[k]);
+      uint32_t f = 0;
+      while ((wmax >> (f + 1)) != words[k]) ++f;
+      fold.out[f] = dst;
+    }
+    sp.bm_words[sp.n_bm] = words[k];
+    sp.bm[sp.n_bm] = dst;
+    ++sp.n_bm;
+  }
+  SizeWindow *d_win = ar.alloc<SizeWindow>(sp.n_sides);
+  h2d(d_win, win.data(), sp.n_sides, st);
+  const SideDesc *sides = sp.d_sides;
+  const uint32_t n_sides = sp.n_sides, seg = sp.seg_blocks;
+  const uint64_t nn = sp.n;
+  const uint32_t *rank = sp.rank;
+  go(L, st, [=](hipStream_t s) {
+    FoldOut f = fold;
+    return launch_build_bitmaps_window(sides, n_sides, seg, nn, rank, d_win, wmax, widest, &f,
+                                       s);
+  });
 }
 
 // The caller's bitmaps of a one-side space (caller order, bits/64 words),
@@ -606,6 +639,7 @@ void space_caller_bitmaps(Space &sp, const uint64_t *bm_caller, uint32_t words, 
   sp.bm_words[0] = words;
   sp.bm[0] = out;
   sp.n_bm = 1;
+  sp.checked = true;
 }
 
 // ------------------------------------------------------------- thresholds
@@ -1087,6 +1121,47 @@ void plan_class(Plan &pl, const Space &R, const Space &C, const TaskIn &tk, uint
   pl.n_tiles = (uint32_t)tiles;
 }
 
+// Size of the set at size-order position pos (counted from the side's
+// base) of side `side`: the largest v whose group starts at or before pos.
+uint32_t size_at(const Space &X, uint32_t side, uint32_t pos) {
+  const uint32_t *t = X.ss(side);
+  uint32_t lo = 0, hi = X.max_size + 1;  // t[lo] <= pos < t[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (t[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Size windows, one per side of X, of the sets that the row blocks of the
+// width slots wider than kCascadeWords read: their rows when `rows` (X is
+// the row space), their columns when `cols` (X is the column space).
+std::vector<SizeWindow> class_windows(const Plan &pl, const std::vector<TaskIn> &tasks,
+                                      const Space &X, bool rows, bool cols,
+                                      const uint32_t *blk_lo, const uint32_t *blk_hi) {
+  std::vector<uint32_t> lo(X.n_sides, 0xFFFFFFFFu), hi(X.n_sides, 0);  // positions [lo, hi)
+  auto add = [&](uint32_t side, uint32_t a, uint32_t b) {
+    const uint32_t base = (uint32_t)X.h_sides[side].base;
+    if (b <= a) return;
+    lo[side] = std::min(lo[side], a - base);
+    hi[side] = std::max(hi[side], b - base);
+  };
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    if (pl.slot_words[k] <= kCascadeWords) continue;
+    for (uint32_t b = blk_lo[k]; b < blk_hi[k]; ++b) {
+      const RowBlock &rb = pl.blocks[b];
+      const TaskIn &tk = tasks[rb.task];
+      if (rows) add(tk.row_side, rb.row0, rb.row_end);
+      if (cols) add(tk.col_side, rb.col_begin, rb.col_end);
+    }
+  }
+  std::vector<SizeWindow> win(X.n_sides, SizeWindow{1, 0});
+  for (uint32_t s = 0; s < X.n_sides; ++s)
+    if (lo[s] < hi[s]) win[s] = SizeWindow{size_at(X, s, lo[s]), size_at(X, s, hi[s] - 1)};
+  return win;
+}
+
 struct Timer {
   hipEvent_t ev[2] = {nullptr, nullptr};
   Timer(const Timer &) = delete;
@@ -1350,6 +1425,43 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
                       (jc.mfma_always || pl.slot_words[k] < kMfmaMinBandWords ||
                        slot_band[k] >= kMfmaMinBand);
   }
+  uint32_t blk_lo[kMaxClasses] = {}, blk_hi[kMaxClasses] = {};  // row blocks of each slot
+  // tiles, slot by slot, task by task.  Unless the caller fixed the tile
+  // width, a slot with little work gets narrower tiles, so that it is cut
+  // into enough tiles to occupy every wave of the GPU.
+  for (uint32_t k = 0; k < pl.n_slots; ++k) {
+    uint32_t tile_cols = jc.tile_cols;
+    if (!jc.tile_cols_fixed && automatic) {
+      // the measured best tile width of the class's width
+      for (int a = 0; a < kNumAuto; ++a)
+        if (kAutoWords[a] == pl.slot_words[k]) tile_cols = kClassTileCols[a];
+    }
+    if (!jc.tile_cols_fixed) {
+      const FilterShape shape = filter_shape(pl.slot_words[k], pl.slot_mfma[k]);
+      const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * kMinSlotTiles);
+      const uint32_t floor_cols = shape.mfma ? kMinTileCols : kMinTileColsValu;
+      tile_cols = (uint32_t)std::max<uint64_t>(floor_cols, std::min<uint64_t>(tile_cols, want));
+    }
+    pl.slot_tile_cols[k] = tile_cols;
+    pl.tile_lo[k] = pl.n_tiles;
+    blk_lo[k] = (uint32_t)pl.blocks.size();
+    const uint64_t ops0 = pl.filter_ops;
+    for (uint32_t t = 0; t < n_tasks; ++t) {
+      uint32_t prev = 0;
+      for (auto &c : classes[t]) {
+        if (c.words == pl.slot_words[k]) {
+          plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
+                     tile_cols, pl.slot_mfma[k], task_band[t]);
+          pl.slot_max_size[k] = std::max(pl.slot_max_size[k], c.max_size);
+        }
+        prev = c.max_size;
+      }
+    }
+    pl.tile_hi[k] = pl.n_tiles;
+    blk_hi[k] = (uint32_t)pl.blocks.size();
+    pl.ops[k] = pl.filter_ops - ops0;
+  }
+
   // the widths to build: every class's, and in automatic mode the widest
   // automatic width for the cascade test of verification (same pass)
   uint32_t bw[kMaxClasses + 1], bb[kMaxClasses + 1], nbw = 0;
@@ -1368,8 +1480,38 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   for (uint32_t k = 0; k < nbw; ++k) {
     if (jc.cols_resident && !C.bitmaps(bw[k])) throw Fail{SSJ_E_UNSUPPORTED};
   }
-  space_bitmaps_multi(R, bw, bb, nbw, ar, ctr, st, L);
-  if (!jc.cols_resident) space_bitmaps_multi(C, bw, bb, nbw, ar, ctr, st, L);
+  // Widths up to the cascade width take one pass over every set of a space
+  // (which also checks the token order).  In automatic mode the wider ones
+  // then take a pass over only the sets their classes' blocks read: the
+  // rows of those blocks and, on the column side, their columns.
+  uint32_t sw[kMaxClasses + 1], sb[kMaxClasses + 1], ns = 0, lw[kMaxClasses + 1], nl = 0;
+  for (uint32_t k = 0; k < nbw; ++k) {
+    const bool window = automatic && bw[k] > kCascadeWords && bw[k] <= kMaxFoldWords &&
+                        (bw[k] & (bw[k] - 1)) == 0 && bb[k] == 64 * bw[k];
+    if (window) {
+      lw[nl++] = bw[k];
+    } else {
+      sw[ns] = bw[k];
+      sb[ns++] = bb[k];
+    }
+  }
+  auto build = [&](Space &X, bool rows, bool cols) {
+    space_bitmaps_multi(X, sw, sb, ns, ar, ctr, st, L);
+    uint32_t need[kMaxClasses + 1], nn = 0;
+    for (uint32_t k = 0; k < nl; ++k)
+      if (!X.bitmaps(lw[k])) need[nn++] = lw[k];
+    if (nn == 0) return;
+    if (X.checked && X.rank) {
+      space_bitmaps_window(X, need, nn, class_windows(pl, tasks, X, rows, cols, blk_lo, blk_hi),
+                           ar, st, L);
+    } else {
+      uint32_t nb[kMaxClasses + 1];
+      for (uint32_t k = 0; k < nn; ++k) nb[k] = 64 * need[k];
+      space_bitmaps_multi(X, need, nb, nn, ar, ctr, st, L);
+    }
+  };
+  build(R, true, &C == &R);
+  if (!jc.cols_resident && &C != &R) build(C, false, true);
   // sign planes for the widths the matrix-core kernel runs (an index holds
   // its own)
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
@@ -1389,39 +1531,6 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
     if (&C != &R && !jc.cols_resident)
       for (const auto &d : C.h_sides)
         go(L, st, [=](hipStream_t s) { return launch_check_sorted(d.offsets, d.tokens, d.n, ctr, s); });
-  }
-  // tiles, slot by slot, task by task.  Unless the caller fixed the tile
-  // width, a slot with little work gets narrower tiles, so that it is cut
-  // into enough tiles to occupy every wave of the GPU.
-  for (uint32_t k = 0; k < pl.n_slots; ++k) {
-    uint32_t tile_cols = jc.tile_cols;
-    if (!jc.tile_cols_fixed && automatic) {
-      // the measured best tile width of the class's width
-      for (int a = 0; a < kNumAuto; ++a)
-        if (kAutoWords[a] == pl.slot_words[k]) tile_cols = kClassTileCols[a];
-    }
-    if (!jc.tile_cols_fixed) {
-      const FilterShape shape = filter_shape(pl.slot_words[k], pl.slot_mfma[k]);
-      const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * kMinSlotTiles);
-      const uint32_t floor_cols = shape.mfma ? kMinTileCols : kMinTileColsValu;
-      tile_cols = (uint32_t)std::max<uint64_t>(floor_cols, std::min<uint64_t>(tile_cols, want));
-    }
-    pl.slot_tile_cols[k] = tile_cols;
-    pl.tile_lo[k] = pl.n_tiles;
-    const uint64_t ops0 = pl.filter_ops;
-    for (uint32_t t = 0; t < n_tasks; ++t) {
-      uint32_t prev = 0;
-      for (auto &c : classes[t]) {
-        if (c.words == pl.slot_words[k]) {
-          plan_class(pl, R, C, tasks[t], t, prev, c.max_size, c.words, pl.slot_bits[k],
-                     tile_cols, pl.slot_mfma[k], task_band[t]);
-          pl.slot_max_size[k] = std::max(pl.slot_max_size[k], c.max_size);
-        }
-        prev = c.max_size;
-      }
-    }
-    pl.tile_hi[k] = pl.n_tiles;
-    pl.ops[k] = pl.filter_ops - ops0;
   }
 
   // rows past the cutoff: their band pairs, probe runs and prefix lengths
@@ -1872,6 +1981,15 @@ void early_bitmaps(Space &sp, const JoinConfig &jc, Arena &ar, JoinCounters *ctr
   space_bitmaps_multi(sp, words, bits, 4, ar, ctr, st);
 }
 
+// The wide bitmaps of verification depend only on the sizes: in automatic
+// mode they are enqueued once the group starts are on the host, so that the
+// device builds them while the host plans (a plan with no cascade test
+// leaves them unused).
+void early_wide(Space &sp, const JoinConfig &jc, Arena &ar, hipStream_t st) {
+  if (jc.b_bits != 0 || jc.survivors_only || !sp.rank) return;
+  space_wide(sp, ar, st);
+}
+
 int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const uint64_t *s_bm,
              bool self, uint32_t b_bits, int sim, uint32_t p, uint32_t q,
              const ssj_options *opts, ssj_pairs *out, ssj_stats *stats, void *hip_stream) {
@@ -1902,6 +2020,8 @@ int join_one(const ssj_sets *R, const uint64_t *r_bm, const ssj_sets *S, const u
     sorted.wait();
     space_finish(A);
     if (!self) space_finish(B);
+    early_wide(A, jc, ar, st);
+    if (!self) early_wide(B, jc, ar, st);
     Space &C = self ? A : B;
     if (r_bm) {
       const uint32_t w = filter_padded_words(b_bits / 64);
@@ -2011,6 +2131,7 @@ int join_tasks(const ssj_sets *rows, uint32_t n, const uint32_t *p, const uint32
     early_bitmaps(A, jc, ar, ctr, st);
     sorted.wait();
     space_finish(A);
+    early_wide(A, jc, ar, st);
     run_join(A, idx ? idx->S : A, tasks, jc, ar, ctr, st, t_prep, jo, stats);
   } catch (const Fail &f) {
     HostPairs::get().release(jo.pairs);

@@ -210,6 +210,21 @@ hipError_t launch_build_bitmaps(const SideDesc *sides, uint32_t n_sides, uint32_
                                 const uint32_t *side_of, uint32_t b_bits, int method,
                                 uint32_t out_words, uint64_t *out, JoinCounters *ctr,
                                 hipStream_t st, const FoldOut *fold = nullptr);
+// Sizes [lo, hi] of the sets of one side that a windowed build covers
+// (none when lo > hi).
+struct SizeWindow {
+  uint32_t lo, hi;
+};
+// Bitmap-Xor bitmaps at out_words = 16 or 32 words (b = 64 out_words) of
+// the sets whose size lies in their side's window win[s], in size order
+// (row rank[g]), and the widths of `fold` (optional, as above) from the same
+// pass.  Rows of the other sets are left as they are.  The token order is
+// not checked: a full build of every set checks it.
+hipError_t launch_build_bitmaps_window(const SideDesc *sides, uint32_t n_sides,
+                                       uint32_t seg_blocks, uint64_t n_total,
+                                       const uint32_t *rank, const SizeWindow *win,
+                                       uint32_t out_words, uint64_t *out, const FoldOut *fold,
+                                       hipStream_t st);
 // workgroups the segmented build uses for a side of n sets
 uint32_t bitmap_seg_blocks(uint64_t n);
 
@@ -245,8 +260,16 @@ constexpr uint32_t kWideMin = 256;
 struct WideRange {
   uint32_t lo, hi, slot, side;
 };
+// The wide range of every side (ranges[s], empty when the side has no set
+// larger than kWideMin) and the per-side lookup of verification (wide_lo:
+// first global position with a wide bitmap, ~0u for none; wide_slot: its
+// slot), from the group starts sstart[s * stride + v] on the device; the
+// slots follow the sides' order.
+hipError_t launch_wide_ranges(const SideDesc *sides, uint32_t n_sides, const uint32_t *sstart,
+                              uint32_t stride, uint32_t max_size, WideRange *ranges,
+                              uint32_t *wide_lo, uint32_t *wide_slot, hipStream_t st);
 // out[slot * kWideWords ...] for every slot in [0, total); ranges sorted by
-// slot, n_ranges >= 1 when total > 0.  perm: size-order position -> caller
+// slot (empty ones allowed), n_ranges >= 1 when total > 0.  perm: size-order position -> caller
 // index within its side.
 hipError_t launch_build_wide(const SideDesc *sides, const uint32_t *perm,
                              const WideRange *ranges, uint32_t n_ranges, uint64_t total,

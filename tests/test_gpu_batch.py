@@ -64,6 +64,53 @@ def test_many_tasks_with_large_sets_match_the_oracle():
         assert st["results"] == sum(len(w) for w in want)
 
 
+def _long_sets():
+    """Instances of long sets (medians 60 to 700 tokens, up to 2000): their
+    widest width classes run past 512 bits."""
+    specs = [(3000, 400.0, (1, 2)), (2500, 150.0, (7, 10)), (6000, 60.0, (4, 5)),
+             (1500, 700.0, (1, 2))]
+    cols = [_col(950 + k, n, universe=40000, hi=2000, median=m, planted=0.2, lo=2)
+            for k, (n, m, _) in enumerate(specs)]
+    return cols, [t for _, _, t in specs]
+
+
+def test_wide_width_classes_match_the_oracle_in_a_call_and_a_plan():
+    """The classes past 512 bits build their bitmaps only for the sets their
+    row blocks read (their rows and the columns of their bands); every
+    instance's pairs equal the oracle's, through the batched call and
+    through a prepared plan's replays."""
+    cols, pq = _long_sets()
+    devs = [_dev(c) for c in cols]
+    ps, qs = [p for p, _ in pq], [q for _, q in pq]
+    want = [oracle.self_join(c.offsets, c.tokens, p, q) for c, (p, q) in zip(cols, pq)]
+    got, st = ssj.ssj_self_join_batch(devs, ps, qs)
+    assert max(st["class_bits"][:st["n_classes"]]) >= 1024, st["class_bits"]
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    with ssj.Plan(devs, ps, qs) as plan:
+        for _ in range(2):
+            again, _ = plan.execute()
+            for g, w in zip(again, want):
+                assert np.array_equal(g, w)
+
+
+def test_wide_width_classes_of_an_rs_join_match_the_oracle():
+    """An R-S join of long sets: the row side's wide bitmaps cover the rows
+    of the wide classes, the column side's the columns of their bands."""
+    r = _col(990, 1200, universe=40000, hi=2000, median=500.0, planted=0.2, lo=2)
+    o = _col(991, 1200, universe=40000, hi=2000, median=400.0, planted=0.2, lo=2)
+    rows = [r.tokens[r.offsets[k]:r.offsets[k + 1]] for k in range(r.n_sets)]
+    other = [o.tokens[o.offsets[k]:o.offsets[k + 1]] for k in range(o.n_sets)]
+    # every second row set, less its largest token, is a column set too
+    s = gen.from_lists([x[:-1].tolist() for x in rows[::2]] + [x.tolist() for x in other])
+    for p, q in [(1, 2), (4, 5)]:
+        want = oracle.rs_join(r.offsets, r.tokens, s.offsets, s.tokens, p, q)
+        assert len(want) > 0
+        got, st = ssj.ssj_rs_join(_dev(r), _dev(s), p, q, b_bits=0)
+        assert max(st["class_bits"][:st["n_classes"]]) >= 1024, st["class_bits"]
+        assert np.array_equal(got, want)
+
+
 def test_batch_equals_single_calls_and_resumes_after_overflow():
     cols = [_col(700 + k, n, universe=300, planted=0.3) for k, n in enumerate((3000, 800, 5000))]
     pq = [(1, 2), (1, 2), (3, 5)]
