@@ -162,16 +162,17 @@ typedef struct {
 #define SSJ_FLAG_CUTOFF 2u
 
 /* Run the bitmap filter on the vector ALUs at every width.  By default the
- * widths b = 64, 128 and 256 run on the matrix cores, which score the
+ * widths of 1, 2, 4, 8 and 16 64-bit words (b = 64, 128, 256, 512, 1024,
+ * and the widths padded to them) run on the matrix cores, which score the
  * Hamming distance of Theorem 1 as a dot product of +-1 vectors (exact);
- * a b = 256 class of fewer than 2^26 band pairs runs on the vector ALUs,
- * whose launch costs less.  The two kernels keep the same pairs.  Changes
- * the work, never the result. */
+ * a class of 4 or more words and fewer than 2^26 band pairs runs on the
+ * vector ALUs, whose launch costs less.  The two kernels keep the same
+ * pairs.  Changes the work, never the result. */
 #define SSJ_FLAG_VALU 4u
 
-/* Run the bitmap filter on the matrix cores at b = 64, 128 and 256 for
- * every width class, whatever its size (with SSJ_FLAG_VALU: invalid).
- * Changes the work, never the result. */
+/* Run the bitmap filter on the matrix cores at the widths above for every
+ * width class, whatever its size (with SSJ_FLAG_VALU: invalid).  Changes
+ * the work, never the result. */
 #define SSJ_FLAG_MFMA 8u
 
 /*

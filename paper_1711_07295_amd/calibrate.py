@@ -53,8 +53,10 @@ TABLE = os.path.join(HERE, "csrc", "autotune_table.h")
 WIDTHS = (64, 128, 256, 512, 1024, 2048)
 # pairs of one step of the filter kernel at each width: the matrix-core
 # kernel scores 32 columns against 32 * RT rows (RT = 6 at 64 bits, 3 at 128
-# and 256), the vector-ALU kernel 64 * R rows against U columns
-PAIRS_PER_STEP = {64: 6144, 128: 3072, 256: 3072, 512: 64, 1024: 64, 2048: 64}
+# and 256, 4 at 512, 2 at 1024), the vector-ALU kernel 64 * R rows against U
+# columns (64 at 2048)
+PAIRS_PER_STEP = {64: 6144, 128: 3072, 256: 3072, 512: 4096, 1024: 2048, 2048: 64}
+MFMA_WIDTHS = (64, 128, 256, 512, 1024)
 TILE_COLS = (1024, 2048, 4096)
 P, Q = 4, 5
 
@@ -104,7 +106,7 @@ def _crowded_tile(b, steps):
         return ssj.to_device(off, tok.reshape(-1))
 
     r, s = sets(64), sets(2048)
-    flags = ssj.SSJ_FLAG_MFMA if b <= 256 else 0
+    flags = ssj.SSJ_FLAG_MFMA if b in MFMA_WIDTHS else 0
     ssj.ssj_rs_join(r, s, 1, 2, b_bits=b, tile_cols=2048, flags=flags)  # warm-up
     runs = [ssj.ssj_rs_join(r, s, 1, 2, b_bits=b, tile_cols=2048, flags=flags)[1]
             for _ in range(steps)]

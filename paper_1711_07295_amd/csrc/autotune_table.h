@@ -14,11 +14,11 @@
 #include <cstdint>
 
 namespace ssj {
-constexpr double kFilterNsPerPair[6] = {2.9672e-05, 4.8339e-05, 1.1220e-04, 8.5153e-04, 2.0138e-03, 5.7949e-03};
-constexpr double kSlowEntryNs = 3.7727e+00;
-constexpr double kSurvivorNs = 7.7342e-02;
-constexpr double kSurvivorWaveNs[6] = {4.6449e+00, 4.5711e+00, 4.6161e+00, 5.6737e+00, 6.9138e+00, 1.7046e+01};
-constexpr double kPairsPerStep[6] = {6144.0, 3072.0, 3072.0, 64.0, 64.0, 64.0};
-constexpr double kClassLaunchNs[6] = {4.0354e+04, 3.1596e+04, 4.0835e+04, 3.5796e+04, 4.2994e+04, 7.3710e+04};
-constexpr uint32_t kClassTileCols[6] = {4096, 4096, 4096, 2048, 1024, 2048};
+constexpr double kFilterNsPerPair[6] = {2.9350e-05, 4.7487e-05, 1.1156e-04, 2.1471e-04, 8.6554e-04, 5.8077e-03};
+constexpr double kSlowEntryNs = 3.9069e+00;
+constexpr double kSurvivorNs = 7.7485e-02;
+constexpr double kSurvivorWaveNs[6] = {4.6819e+00, 4.5574e+00, 4.6085e+00, 5.2081e+00, 5.5160e+00, 1.6888e+01};
+constexpr double kPairsPerStep[6] = {6144.0, 3072.0, 3072.0, 4096.0, 2048.0, 64.0};
+constexpr double kClassLaunchNs[6] = {4.0475e+04, 3.1196e+04, 4.1075e+04, 3.5995e+04, 4.2435e+04, 7.4510e+04};
+constexpr uint32_t kClassTileCols[6] = {4096, 4096, 4096, 4096, 4096, 2048};
 }  // namespace ssj

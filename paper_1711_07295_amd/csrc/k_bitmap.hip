@@ -321,9 +321,22 @@ hipError_t launch_method(bool pow2, hipStream_t st, const SideDesc *sides, uint3
   return hipGetLastError();
 }
 
+// fp4 nibbles of one 32-bit half x of a bitmap block: +1 (0x2) for a set
+// bit, -1 (0xA) for a clear one; bit 8e+m of the half in nibble m of dword e.
+__device__ __forceinline__ uint4 sign_nibbles(uint32_t x) {
+  uint32_t d[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t spread = 0;  // bit m of byte e at bit 4m
+#pragma unroll
+    for (int m = 0; m < 8; ++m) spread |= ((x >> (8 * e + m)) & 1u) << (4 * m);
+    d[e] = 0xAAAAAAAAu ^ (spread << 3);
+  }
+  return make_uint4(d[0], d[1], d[2], d[3]);
+}
+
 // Sign planes: one thread per (set, 64-bit block, half), for n + kSignPad
-// sets: the sets from n on are all zero.  Each half of 32 bits becomes four dwords of fp4 nibbles,
-// +1 (0x2) for a set bit and -1 (0xA) for a clear one.
+// sets: the sets from n on are all zero.
 __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restrict__ bm,
                                                           uint32_t words, uint64_t n,
                                                           uint4 *__restrict__ planes) {
@@ -333,19 +346,32 @@ __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restr
   const uint64_t sw = t >> 1;
   const uint64_t s = sw / words;
   const uint32_t kb = (uint32_t)(sw - s * words);
-  uint4 out = make_uint4(0u, 0u, 0u, 0u);
-  if (s < n) {
-    const uint32_t x = (uint32_t)(bm[sw] >> (32 * h));
-    uint32_t d[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      uint32_t spread = 0;  // bit m of byte e at bit 4m
-#pragma unroll
-      for (int m = 0; m < 8; ++m) spread |= ((x >> (8 * e + m)) & 1u) << (4 * m);
-      d[e] = 0xAAAAAAAAu ^ (spread << 3);
-    }
-    out = make_uint4(d[0], d[1], d[2], d[3]);
+  const uint4 out = s < n ? sign_nibbles((uint32_t)(bm[sw] >> (32 * h))) : make_uint4(0u, 0u, 0u, 0u);
+  planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
+}
+
+// Sign planes of the sets in the ranges only (the padding sets n .. n +
+// kSignPad - 1 are one of them): element e of the ranges' concatenation is
+// position ranges[r].lo + e - ranges[r].first of the range r holding it.
+__global__ __launch_bounds__(kBlock) void k_expand_signs_ranges(
+    const uint64_t *__restrict__ bm, uint32_t words, uint64_t n,
+    const PosRange *__restrict__ ranges, uint32_t n_ranges, uint64_t total,
+    uint4 *__restrict__ planes) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= total * words * 2) return;
+  const uint32_t h = (uint32_t)(t & 1);
+  const uint64_t ew = t >> 1;
+  const uint64_t e = ew / words;
+  const uint32_t kb = (uint32_t)(ew - e * words);
+  uint32_t lo = 0, hi = n_ranges;  // the last range whose first element is <= e
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ranges[mid].first <= e) lo = mid;
+    else hi = mid;
   }
+  const uint64_t s = ranges[lo].lo + (e - ranges[lo].first);
+  const uint4 out = s < n ? sign_nibbles((uint32_t)(bm[s * words + kb] >> (32 * h)))
+                          : make_uint4(0u, 0u, 0u, 0u);
   planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
 }
 
@@ -523,6 +549,17 @@ hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, u
   const uint64_t total = (n + kSignPad) * words * 2;
   hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, st, bm, words, n, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_signs_ranges(const uint64_t *bm, uint32_t words, uint64_t n,
+                                      const PosRange *ranges, uint32_t n_ranges, uint64_t total,
+                                      uint4 *planes, hipStream_t st) {
+  if (words == 0 || n_ranges == 0) return hipErrorInvalidValue;
+  const uint64_t threads = total * words * 2;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_signs_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, st, bm, words, n, ranges, n_ranges, total, planes);
   return hipGetLastError();
 }
 

@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-core filter (b = 64, 128, 256).
+// Matrix-core filter (b = 64, 128, 256, 512, 1024).
 //
 // With every bit of a bitmap mapped to +1 (set) or -1 (clear), the dot
 // product of two such vectors over K bits is K - 2 popcount(b_r xor b_s), so
@@ -940,13 +940,18 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
 // Matrix-core kernels: (words, row tiles of 32 per wave).  At b = 64 six row
 // tiles (three waves per SIMD) beat four (four waves per SIMD): a column
 // step's loads, loop control and tests serve six products instead of four.
-// (b = 512 stays on the vector ALUs: with eight 64-bit blocks per column a
-// step streams 8 bytes of column planes per pair at the row-tile counts the
-// registers allow, more than L2 delivers; the vector-ALU kernel is faster.)
+// At b = 512 and 1024 a column step streams b/2 bytes of sign planes per
+// column, shared by the 32 RT rows of the wave: four and two row tiles
+// (one wave per SIMD, the register file's other half holding rows and
+// column buffers) keep that stream within what L2 delivers, and beat the
+// vector ALUs by 3.2x and 1.8x.  b = 2048 stays on the vector ALUs: its
+// ring of column buffers alone would fill the registers.
 #define SSJ_MFMA_SHAPES(X) \
   X(1, 6)                  \
   X(2, 3)                  \
-  X(4, 3)
+  X(4, 3)                  \
+  X(8, 4)                  \
+  X(16, 2)
 
 }  // namespace
 

@@ -24,6 +24,7 @@
 #include <exception>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -58,8 +59,8 @@ constexpr uint32_t kPlanThreads = 8;
 constexpr uint64_t kPlanThreadSizes = 65536;
 constexpr uint32_t kMinTileCols = 64;
 constexpr uint32_t kMinTileColsValu = 32;
-// A b = 256 class (four words) of fewer band pairs than this runs on the
-// vector ALUs: there the matrix-core launch has the larger fixed cost
+// A class of four or more words (b >= 256) and fewer band pairs than this
+// runs on the vector ALUs: there the matrix-core launch has the larger fixed cost
 // (about 0.12 ms against 0.07 ms for a class of 1.6e6 pairs), and its sign
 // planes need not be built.  Narrower classes stay on the matrix cores at
 // any size: a query of a few sets against a large index sweeps long column
@@ -493,15 +494,30 @@ void space_bitmaps(Space &sp, uint32_t words, uint32_t bits, Arena &ar, JoinCoun
   sp.checked = true;
 }
 
-// Sign planes of the space's bitmaps at `words` words (built before).
-void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st, Launcher *L = nullptr) {
+// Sign planes of the space's bitmaps at `words` words (built before): of
+// every set, or only of the positions in `ranges` (the other planes stay
+// unwritten, so only those positions may be read).
+void space_signs(Space &sp, uint32_t words, Arena &ar, hipStream_t st, Launcher *L = nullptr,
+                 const std::vector<PosRange> *ranges = nullptr) {
   for (uint32_t k = 0; k < sp.n_bm; ++k) {
     if (sp.bm_words[k] != words) continue;
     if (sp.sg[k]) return;
     uint4 *planes = ar.alloc<uint4>((sp.n + kSignPad) * words * 2);
     const uint64_t *bm = sp.bm[k];
     const uint64_t n = sp.n;
-    go(L, st, [=](hipStream_t s) { return launch_expand_signs(bm, words, n, planes, s); });
+    if (ranges && !ranges->empty()) {
+      const PosRange *d_ranges = nullptr;
+      PosRange *up = ar.alloc<PosRange>(ranges->size());
+      h2d(up, ranges->data(), ranges->size(), st);
+      d_ranges = up;
+      const uint32_t nr = (uint32_t)ranges->size();
+      const uint64_t total = (uint64_t)ranges->back().first + kSignPad;
+      go(L, st, [=](hipStream_t s) {
+        return launch_expand_signs_ranges(bm, words, n, d_ranges, nr, total, planes, s);
+      });
+    } else {
+      go(L, st, [=](hipStream_t s) { return launch_expand_signs(bm, words, n, planes, s); });
+    }
     sp.sg[k] = planes;
     return;
   }
@@ -772,11 +788,19 @@ struct SizeOdds {
 
 // SizeOdds of every size up to max_rows, per (function, threshold), kept
 // and extended as larger sizes come up.
-std::vector<SizeOdds> false_survivor_odds(uint32_t max_rows, int sim, uint64_t p, uint64_t q) {
+std::shared_ptr<const std::vector<SizeOdds>> false_survivor_odds(uint32_t max_rows, int sim,
+                                                                 uint64_t p, uint64_t q) {
   static std::mutex mu;
-  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>, std::vector<SizeOdds>> memo;
+  static std::map<std::pair<int, std::pair<uint64_t, uint64_t>>,
+                  std::shared_ptr<const std::vector<SizeOdds>>>
+      memo;
   std::lock_guard<std::mutex> lk(mu);
-  std::vector<SizeOdds> &v = memo[{sim, {p, q}}];
+  std::shared_ptr<const std::vector<SizeOdds>> &slot = memo[{sim, {p, q}}];
+  if (slot && slot->size() > max_rows) return slot;  // shared, never copied: many tasks read it
+  // a longer table replaces the shorter one; tasks that hold the old one keep it
+  auto grown = std::make_shared<std::vector<SizeOdds>>();
+  if (slot) *grown = *slot;
+  std::vector<SizeOdds> &v = *grown;
   if (v.empty()) v.push_back({});  // size 0: never pairs
   for (uint32_t a = (uint32_t)v.size(); a <= max_rows; ++a) {
     const uint64_t L = 2ull * a;
@@ -792,7 +816,8 @@ std::vector<SizeOdds> false_survivor_odds(uint32_t max_rows, int sim, uint64_t p
     }
     v.push_back(o);
   }
-  return std::vector<SizeOdds>(v.begin(), v.begin() + max_rows + 1);
+  slot = grown;
+  return slot;
 }
 
 // A task's rows of one size: their band pairs and their number.
@@ -807,12 +832,13 @@ struct SizeLoad {
 std::vector<WidthClass> choose_classes(const std::vector<SizeLoad> &load, int sim, uint64_t p,
                                        uint64_t q, double waves) {
   const uint32_t n = std::max<uint32_t>((uint32_t)load.size() - 1, 1);
-  const auto odds = false_survivor_odds(n, sim, p, q);
+  const auto odds_table = false_survivor_odds(n, sim, p, q);
+  const std::vector<SizeOdds> &odds = *odds_table;
   // tile shape of each width's kernel (waves: the waves of a filter grid)
   double tile_rows[kNumAuto], tile_cols[kNumAuto];
   for (int k = 0; k < kNumAuto; ++k) {
     const uint32_t w = kAutoWords[k];
-    tile_rows[k] = std::max<uint32_t>(1, filter_shape(filter_padded_words(w), w < 8).rows);
+    tile_rows[k] = std::max<uint32_t>(1, filter_shape(filter_padded_words(w), true).rows);
     tile_cols[k] = kClassTileCols[k];
   }
   std::vector<uint32_t> sizes;
@@ -1134,13 +1160,16 @@ uint32_t size_at(const Space &X, uint32_t side, uint32_t pos) {
   return lo;
 }
 
-// Size windows, one per side of X, of the sets that the row blocks of the
-// width slots wider than kCascadeWords read: their rows when `rows` (X is
-// the row space), their columns when `cols` (X is the column space).
-std::vector<SizeWindow> class_windows(const Plan &pl, const std::vector<TaskIn> &tasks,
-                                      const Space &X, bool rows, bool cols,
-                                      const uint32_t *blk_lo, const uint32_t *blk_hi) {
-  std::vector<uint32_t> lo(X.n_sides, 0xFFFFFFFFu), hi(X.n_sides, 0);  // positions [lo, hi)
+// Positions [lo, hi) (counted from each side's base; lo > hi when none) of
+// the sets that the row blocks of the width slots chosen by use(words) read,
+// one hull per side of X: their rows when `rows` (X is the row space), their
+// columns when `cols` (X is the column space).
+template <class Use>
+void block_hulls(const Plan &pl, const std::vector<TaskIn> &tasks, const Space &X, bool rows,
+                 bool cols, const uint32_t *blk_lo, const uint32_t *blk_hi, Use use,
+                 std::vector<uint32_t> &lo, std::vector<uint32_t> &hi) {
+  lo.assign(X.n_sides, 0xFFFFFFFFu);
+  hi.assign(X.n_sides, 0);
   auto add = [&](uint32_t side, uint32_t a, uint32_t b) {
     const uint32_t base = (uint32_t)X.h_sides[side].base;
     if (b <= a) return;
@@ -1148,7 +1177,7 @@ std::vector<SizeWindow> class_windows(const Plan &pl, const std::vector<TaskIn> 
     hi[side] = std::max(hi[side], b - base);
   };
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
-    if (pl.slot_words[k] <= kCascadeWords) continue;
+    if (!use(pl.slot_words[k])) continue;
     for (uint32_t b = blk_lo[k]; b < blk_hi[k]; ++b) {
       const RowBlock &rb = pl.blocks[b];
       const TaskIn &tk = tasks[rb.task];
@@ -1156,10 +1185,49 @@ std::vector<SizeWindow> class_windows(const Plan &pl, const std::vector<TaskIn> 
       if (cols) add(tk.col_side, rb.col_begin, rb.col_end);
     }
   }
+}
+
+// Size windows, one per side of X, of the sets that the row blocks of the
+// width slots wider than kCascadeWords read (as block_hulls).
+std::vector<SizeWindow> class_windows(const Plan &pl, const std::vector<TaskIn> &tasks,
+                                      const Space &X, bool rows, bool cols,
+                                      const uint32_t *blk_lo, const uint32_t *blk_hi) {
+  std::vector<uint32_t> lo, hi;
+  block_hulls(pl, tasks, X, rows, cols, blk_lo, blk_hi,
+              [](uint32_t w) { return w > kCascadeWords; }, lo, hi);
   std::vector<SizeWindow> win(X.n_sides, SizeWindow{1, 0});
   for (uint32_t s = 0; s < X.n_sides; ++s)
     if (lo[s] < hi[s]) win[s] = SizeWindow{size_at(X, s, lo[s]), size_at(X, s, hi[s] - 1)};
   return win;
+}
+
+// Positions of X whose sign planes at `words` words the matrix-core filter
+// reads: the hulls of the blocks of that width (as block_hulls), each
+// extended by the kSignPad - 1 columns a step loads past its group's end,
+// merged, and then the padding sets [n, n + kSignPad).
+std::vector<PosRange> sign_ranges(const Plan &pl, const std::vector<TaskIn> &tasks,
+                                  const Space &X, bool rows, bool cols, const uint32_t *blk_lo,
+                                  const uint32_t *blk_hi, uint32_t words) {
+  std::vector<uint32_t> lo, hi;
+  block_hulls(pl, tasks, X, rows, cols, blk_lo, blk_hi,
+              [words](uint32_t w) { return w == words; }, lo, hi);
+  std::vector<std::pair<uint64_t, uint64_t>> iv;
+  for (uint32_t s = 0; s < X.n_sides; ++s) {
+    if (lo[s] >= hi[s]) continue;
+    const uint64_t base = X.h_sides[s].base;
+    iv.emplace_back(base + lo[s], std::min<uint64_t>(base + hi[s] + kSignPad - 1, X.n));
+  }
+  std::sort(iv.begin(), iv.end());
+  std::vector<PosRange> out;
+  uint64_t total = 0;
+  for (size_t i = 0; i < iv.size();) {
+    uint64_t a = iv[i].first, b = iv[i].second;
+    for (++i; i < iv.size() && iv[i].first <= b; ++i) b = std::max(b, iv[i].second);
+    out.push_back(PosRange{(uint32_t)a, (uint32_t)b, (uint32_t)total, 0});
+    total += b - a;
+  }
+  out.push_back(PosRange{(uint32_t)X.n, (uint32_t)(X.n + kSignPad), (uint32_t)total, 0});
+  return out;
 }
 
 struct Timer {
@@ -1514,14 +1582,17 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   if (!jc.cols_resident && &C != &R) build(C, false, true);
   // sign planes for the widths the matrix-core kernel runs (an index holds
   // its own)
+  // of only the sets that the width's blocks read
   for (uint32_t k = 0; k < pl.n_slots; ++k) {
     const uint32_t w = pl.slot_words[k];
     if (!pl.slot_mfma[k]) continue;
-    space_signs(R, w, ar, st, L);
+    const std::vector<PosRange> rr = sign_ranges(pl, tasks, R, true, &C == &R, blk_lo, blk_hi, w);
+    space_signs(R, w, ar, st, L, &rr);
     if (jc.cols_resident) {
       if (!C.signs(w)) throw Fail{SSJ_E_UNSUPPORTED};
-    } else {
-      space_signs(C, w, ar, st, L);
+    } else if (&C != &R) {
+      const std::vector<PosRange> cr = sign_ranges(pl, tasks, C, false, true, blk_lo, blk_hi, w);
+      space_signs(C, w, ar, st, L, &cr);
     }
   }
   if (pl.n_slots == 0) {

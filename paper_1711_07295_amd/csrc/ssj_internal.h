@@ -250,6 +250,18 @@ constexpr uint32_t kSignPad = 96;
 hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
                                hipStream_t st);
 
+// Positions [lo, hi) of a size-ordered space, at elements [first, first +
+// hi - lo) of the concatenation of a list of such ranges.
+struct PosRange {
+  uint32_t lo, hi, first, pad;
+};
+// Sign planes (layout as above) of only the positions in `ranges` (sorted
+// by position and by first, disjoint, `total` positions in all); positions
+// from n on are written as zeros, so the list holds [n, n + kSignPad).
+hipError_t launch_expand_signs_ranges(const uint64_t *bm, uint32_t words, uint64_t n,
+                                      const PosRange *ranges, uint32_t n_ranges, uint64_t total,
+                                      uint4 *planes, hipStream_t st);
+
 // Wide bitmaps for verification: Bitmap-Xor at 64 * kWideWords bits of the
 // sets larger than kWideMin (where the widest automatic width no longer
 // prunes: its bits saturate).  In size order those sets are a suffix of each

@@ -37,8 +37,9 @@ from . import DeviceSets, Index
 # Device bytes a call needs per admitted set and per token: the uploaded
 # offsets (8) and tokens (4 per token); four uint32 index arrays (16), two
 # sort keys and their scratch (24), bitmaps at 64, 128, ..., 2048 bits (504),
-# sign planes of the matrix-core widths at up to 32+64+128 bytes (224).
-BYTES_PER_SET = 776
+# sign planes of the matrix-core widths at up to 32+64+128+256+512 bytes
+# (992; allocated for every set even where only some are written).
+BYTES_PER_SET = 1544
 BYTES_PER_TOKEN = 4
 # Per queue slot: the (row, column) entry, a slot for a long pair that
 # verification defers, and a result key, 8 bytes each.
