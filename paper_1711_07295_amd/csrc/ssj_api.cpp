@@ -242,6 +242,20 @@ class Arena {
       if (owned_) (void)hipFree(c.first);
       else ChunkCache::get().give(dev_, c.first, c.second);
     }
+    // an owned arena's work has finished by now: its owner synchronised
+    // after the uploads, and hipFree waits for the device
+    for (void *p : staged_) HostPairs::get().release(p);
+  }
+  // Host memory for an upload from this arena's stream: page-locked when
+  // large (the copy then runs asynchronously, without a staged copy that
+  // waits for the work queued before it), kept until the arena ends.
+  template <class T>
+  T *stage(uint64_t n) {
+    const uint64_t bytes = std::max<uint64_t>(n, 1) * sizeof(T);
+    void *p = HostPairs::get().alloc((bytes + sizeof(ssj_pair) - 1) / sizeof(ssj_pair));
+    if (!p) throw std::bad_alloc();
+    staged_.push_back(p);
+    return static_cast<T *>(p);
   }
   template <class T>
   T *alloc(uint64_t n) {
@@ -280,6 +294,7 @@ class Arena {
   bool fixed_ = false;
   int dev_ = 0;
   std::vector<std::pair<void *, uint64_t>> chunks_;
+  std::vector<void *> staged_;  // host upload buffers (HostPairs)
   char *next_ = nullptr;
   uint64_t left_ = 0;
 };
@@ -1024,7 +1039,9 @@ struct Plan {
   uint64_t ops[kMaxClasses] = {};
 };
 
-// The task's threshold tables, appended to pl.tables.
+// Threshold tables for sizes up to a_max (rows) and c_max (columns),
+// appended to pl.tables; their offsets and the function and threshold go
+// into td.
 void add_tables(Plan &pl, TaskDesc &td, uint64_t a_max, uint64_t c_max, int sim, uint64_t p,
                 uint64_t q) {
   const uint64_t nL = sim == SSJ_SIM_COSINE ? 1 : a_max + c_max + 1, nA = a_max + 1;
@@ -1381,14 +1398,28 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   std::vector<uint32_t> side_task(R.n_sides, 0xFFFFFFFFu);
   const uint32_t wpad = automatic ? 0 : filter_padded_words(jc.b_bits / 64);
   if (!automatic && !wpad) throw Fail{SSJ_E_UNSUPPORTED};
+  // Threshold tables depend on the function and threshold alone (entry L or
+  // a holds the same value in any task): tasks that share them share one
+  // copy, long enough for the largest sizes among those tasks.
+  using TableKey = std::pair<int, std::pair<uint64_t, uint64_t>>;
+  std::map<TableKey, std::pair<uint32_t, uint32_t>> table_sizes;  // largest a_max, c_max
+  for (const TaskIn &tk : tasks) {
+    auto &m = table_sizes[{tk.sim, {tk.p, tk.q}}];
+    m.first = std::max(m.first, R.side_max[tk.row_side]);
+    m.second = std::max(m.second, C.side_max[tk.col_side]);
+  }
+  std::map<TableKey, TaskDesc> shared_tables;
+  for (const auto &e : table_sizes)
+    add_tables(pl, shared_tables[e.first], e.second.first, e.second.second, e.first.first,
+               e.first.second.first, e.first.second.second);
   for (uint32_t k = 0; k < n_tasks; ++k) {
     const TaskIn &tk = tasks[k];
     const uint32_t key_side = tk.row_side;
     if (side_task[key_side] != 0xFFFFFFFFu) throw Fail{SSJ_E_INVALID};
     side_task[key_side] = k;
     TaskDesc &td = pl.tasks[k];
-    const uint32_t a_max = R.side_max[tk.row_side], c_max = C.side_max[tk.col_side];
-    add_tables(pl, td, a_max, c_max, tk.sim, tk.p, tk.q);
+    const uint32_t a_max = R.side_max[tk.row_side];
+    td = shared_tables.at({tk.sim, {tk.p, tk.q}});
     td.row_side = tk.row_side;
     td.col_side = tk.col_side;
     td.col_base = (uint32_t)C.h_sides[tk.col_side].base;
@@ -1662,15 +1693,15 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
   constexpr uint64_t kBlockWords = sizeof(RowBlock) / 4, kTaskWords = sizeof(TaskDesc) / 4;
   static_assert(sizeof(RowBlock) % 8 == 0 && sizeof(TaskDesc) % 8 == 0, "8-byte layout");
   const uint64_t nB = pl.blocks.size(), nT = pl.tasks.size(), nS = side_task.size();
-  std::vector<uint32_t> packed(kBlockWords * nB + kTaskWords * nT + nS + pl.tables.size());
-  uint32_t *hp = packed.data();
+  const uint64_t n_packed = kBlockWords * nB + kTaskWords * nT + nS + pl.tables.size();
+  uint32_t *hp = ar.stage<uint32_t>(n_packed);
   std::memcpy(hp, pl.blocks.data(), nB * sizeof(RowBlock));
   std::memcpy(hp + kBlockWords * nB, pl.tasks.data(), nT * sizeof(TaskDesc));
   std::memcpy(hp + kBlockWords * nB + kTaskWords * nT, side_task.data(), nS * 4);
   std::memcpy(hp + kBlockWords * nB + kTaskWords * nT + nS, pl.tables.data(),
               pl.tables.size() * 4);
-  uint32_t *d_packed = ar.alloc<uint32_t>(packed.size());
-  h2d(d_packed, packed.data(), packed.size(), st);
+  uint32_t *d_packed = ar.alloc<uint32_t>(n_packed);
+  h2d(d_packed, hp, n_packed, st);
   const RowBlock *d_blocks = reinterpret_cast<const RowBlock *>(d_packed);
   const TaskDesc *d_tasks = reinterpret_cast<const TaskDesc *>(d_packed + kBlockWords * nB);
   const uint32_t *d_side_task = d_packed + kBlockWords * nB + kTaskWords * nT;
