@@ -52,10 +52,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "autotune_table.h")
 WIDTHS = (64, 128, 256, 512, 1024, 2048)
 # pairs of one step of the filter kernel at each width: the matrix-core
-# kernel scores 32 columns against 32 * RT rows (RT = 6 at 64 bits, 3 at 128
-# and 256, 4 at 512, 2 at 1024), the vector-ALU kernel 64 * R rows against U
+# kernel scores 32 columns against 32 * RT rows (RT = 6 at 64 bits, 4 at 128,
+# 5 at 256, 4 at 512, 2 at 1024), the vector-ALU kernel 64 * R rows against U
 # columns (64 at 2048)
-PAIRS_PER_STEP = {64: 6144, 128: 3072, 256: 3072, 512: 4096, 1024: 2048, 2048: 64}
+PAIRS_PER_STEP = {64: 6144, 128: 4096, 256: 5120, 512: 4096, 1024: 2048, 2048: 64}
 MFMA_WIDTHS = (64, 128, 256, 512, 1024)
 TILE_COLS = (1024, 2048, 4096)
 P, Q = 4, 5

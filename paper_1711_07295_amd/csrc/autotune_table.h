@@ -14,11 +14,11 @@
 #include <cstdint>
 
 namespace ssj {
-constexpr double kFilterNsPerPair[6] = {2.9350e-05, 4.7487e-05, 1.1156e-04, 2.1471e-04, 8.6554e-04, 5.8077e-03};
-constexpr double kSlowEntryNs = 3.9069e+00;
-constexpr double kSurvivorNs = 7.7485e-02;
-constexpr double kSurvivorWaveNs[6] = {4.6819e+00, 4.5574e+00, 4.6085e+00, 5.2081e+00, 5.5160e+00, 1.6888e+01};
-constexpr double kPairsPerStep[6] = {6144.0, 3072.0, 3072.0, 4096.0, 2048.0, 64.0};
-constexpr double kClassLaunchNs[6] = {4.0475e+04, 3.1196e+04, 4.1075e+04, 3.5995e+04, 4.2435e+04, 7.4510e+04};
+constexpr double kFilterNsPerPair[6] = {2.9462e-05, 4.2423e-05, 7.9398e-05, 2.1332e-04, 8.6747e-04, 5.7976e-03};
+constexpr double kSlowEntryNs = 3.6491e+00;
+constexpr double kSurvivorNs = 7.7376e-02;
+constexpr double kSurvivorWaveNs[6] = {4.5648e+00, 4.4890e+00, 4.5477e+00, 5.1089e+00, 5.3780e+00, 1.6892e+01};
+constexpr double kPairsPerStep[6] = {6144.0, 4096.0, 5120.0, 4096.0, 2048.0, 64.0};
+constexpr double kClassLaunchNs[6] = {4.1035e+04, 3.5716e+04, 4.1474e+04, 3.5595e+04, 4.2834e+04, 7.3631e+04};
 constexpr uint32_t kClassTileCols[6] = {4096, 4096, 4096, 4096, 4096, 2048};
 }  // namespace ssj

@@ -133,17 +133,48 @@ __global__ __launch_bounds__(kBlock) void k_build_bitmaps_seg(
     for (uint32_t i = threadIdx.x; i < ns * 2 * WO; i += kBlock) sbits[i] = 0;
     __syncthreads();
     const uint64_t nt = soff[ns];
-    for (uint64_t g = threadIdx.x; g < nt; g += kBlock) {
-      uint32_t lo = 0, hi = ns;  // soff[lo] <= g < soff[hi]
+    // Each thread takes four consecutive tokens at a time, from the
+    // 16-byte boundary at or before the run's start: one 16-byte load
+    // (scalar loads at the array's end or for an unaligned array), one
+    // binary search for the first token's set, then a step to the next set
+    // wherever a set ends.  Each token is checked against the one before it
+    // in its set.
+    const uint64_t head = t0 & 3, a0 = t0 - head;  // tokens[a0] is 16-byte aligned
+    const bool vec = (reinterpret_cast<uintptr_t>(tokens) & 15) == 0;
+    for (uint64_t c = (uint64_t)threadIdx.x * 4; c < nt + head; c += 4 * kBlock) {
+      uint32_t v[4];
+      if (vec && a0 + c + 4 <= sd.n_tokens) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(tokens + a0 + c);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = a0 + c + k < sd.n_tokens ? tokens[a0 + c + k] : 0u;
+      }
+      // tokens g = c + k - head of the run, for k with 0 <= g < nt
+      const uint64_t kfirst = c < head ? head - c : 0;
+      const uint64_t gfirst = c + kfirst - head;
+      uint32_t lo = 0, hi = ns;  // soff[lo] <= gfirst < soff[hi]
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (soff[mid] <= g) lo = mid; else hi = mid;
+        if (soff[mid] <= gfirst) lo = mid; else hi = mid;
       }
-      const uint32_t v = tokens[t0 + g];
-      if (g + 1 < soff[lo + 1]) unsorted |= !(v < tokens[t0 + g + 1]);
-      const uint32_t s = POW2 ? (v & mask) : (v % b_bits);
-      if (METHOD == SSJ_BM_XOR) atomicXor(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
-      else atomicOr(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if ((uint64_t)k < kfirst) continue;
+        const uint64_t g = c + k - head;
+        if (g >= nt) break;
+        while (soff[lo + 1] <= g) ++lo;
+        if (g > soff[lo]) {
+          const uint32_t prev = (uint64_t)k > kfirst ? v[k - 1] : tokens[t0 + g - 1];
+          unsorted |= !(prev < v[k]);
+        }
+        const uint32_t s = POW2 ? (v[k] & mask) : (v[k] % b_bits);
+        if (METHOD == SSJ_BM_XOR) atomicXor(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+        else atomicOr(&sbits[lo * 2 * WO + (s >> 5)], 1u << (s & 31));
+      }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < ns * WO; i += kBlock) {

@@ -940,7 +940,9 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
 // Matrix-core kernels: (words, row tiles of 32 per wave).  At b = 64 six row
 // tiles (three waves per SIMD) beat four (four waves per SIMD): a column
 // step's loads, loop control and tests serve six products instead of four.
-// At b = 512 and 1024 a column step streams b/2 bytes of sign planes per
+// At b = 128 four row tiles (three waves per SIMD) and at b = 256 five (two
+// waves per SIMD) are the most the registers allow at that occupancy; six,
+// at one wave fewer per SIMD, were slower.  At b = 512 and 1024 a column step streams b/2 bytes of sign planes per
 // column, shared by the 32 RT rows of the wave: four and two row tiles
 // (one wave per SIMD, the register file's other half holding rows and
 // column buffers) keep that stream within what L2 delivers, and beat the
@@ -948,8 +950,8 @@ hipError_t launch_mfma(dim3 grid, hipStream_t st, const FilterArgs &a) {
 // ring of column buffers alone would fill the registers.
 #define SSJ_MFMA_SHAPES(X) \
   X(1, 6)                  \
-  X(2, 3)                  \
-  X(4, 3)                  \
+  X(2, 4)                  \
+  X(4, 5)                  \
   X(8, 4)                  \
   X(16, 2)
 
