@@ -366,44 +366,48 @@ __device__ __forceinline__ uint4 sign_nibbles(uint32_t x) {
   return make_uint4(d[0], d[1], d[2], d[3]);
 }
 
-// Sign planes: one thread per (set, 64-bit block, half), for n + kSignPad
-// sets: the sets from n on are all zero.
+// Sign planes of set s, half h (zeros for s >= n): the thread reads the
+// set's words in turn and writes block kb's half to plane kb, so that the
+// threads of a wave (consecutive sets and halves) write one contiguous run
+// of each plane.
+__device__ __forceinline__ void expand_set(const uint64_t *__restrict__ bm, uint32_t words,
+                                           uint64_t n, uint64_t s, uint32_t h,
+                                           uint4 *__restrict__ planes) {
+  for (uint32_t kb = 0; kb < words; ++kb) {
+    const uint4 out = s < n ? sign_nibbles((uint32_t)(bm[s * words + kb] >> (32 * h)))
+                            : make_uint4(0u, 0u, 0u, 0u);
+    planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
+  }
+}
+
+// Sign planes: one thread per (set, half), for n + kSignPad sets: the sets
+// from n on are all zero.
 __global__ __launch_bounds__(kBlock) void k_expand_signs(const uint64_t *__restrict__ bm,
                                                           uint32_t words, uint64_t n,
                                                           uint4 *__restrict__ planes) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (n + kSignPad) * words * 2) return;
-  const uint32_t h = (uint32_t)(t & 1);
-  const uint64_t sw = t >> 1;
-  const uint64_t s = sw / words;
-  const uint32_t kb = (uint32_t)(sw - s * words);
-  const uint4 out = s < n ? sign_nibbles((uint32_t)(bm[sw] >> (32 * h))) : make_uint4(0u, 0u, 0u, 0u);
-  planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
+  if (t >= (n + kSignPad) * 2) return;
+  expand_set(bm, words, n, t >> 1, (uint32_t)(t & 1), planes);
 }
 
 // Sign planes of the sets in the ranges only (the padding sets n .. n +
-// kSignPad - 1 are one of them): element e of the ranges' concatenation is
-// position ranges[r].lo + e - ranges[r].first of the range r holding it.
+// kSignPad - 1 are one of them), one thread per (set, half): element e of
+// the ranges' concatenation is position ranges[r].lo + e - ranges[r].first
+// of the range r holding it.
 __global__ __launch_bounds__(kBlock) void k_expand_signs_ranges(
     const uint64_t *__restrict__ bm, uint32_t words, uint64_t n,
     const PosRange *__restrict__ ranges, uint32_t n_ranges, uint64_t total,
     uint4 *__restrict__ planes) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= total * words * 2) return;
-  const uint32_t h = (uint32_t)(t & 1);
-  const uint64_t ew = t >> 1;
-  const uint64_t e = ew / words;
-  const uint32_t kb = (uint32_t)(ew - e * words);
+  if (t >= total * 2) return;
+  const uint64_t e = t >> 1;
   uint32_t lo = 0, hi = n_ranges;  // the last range whose first element is <= e
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (ranges[mid].first <= e) lo = mid;
     else hi = mid;
   }
-  const uint64_t s = ranges[lo].lo + (e - ranges[lo].first);
-  const uint4 out = s < n ? sign_nibbles((uint32_t)(bm[s * words + kb] >> (32 * h)))
-                          : make_uint4(0u, 0u, 0u, 0u);
-  planes[((uint64_t)kb * (n + kSignPad) + s) * 2 + h] = out;
+  expand_set(bm, words, n, ranges[lo].lo + (e - ranges[lo].first), (uint32_t)(t & 1), planes);
 }
 
 // The wide ranges of every side from its group starts, on the device (one
@@ -577,7 +581,7 @@ hipError_t launch_gather_bitmaps(const uint64_t *in, const uint32_t *perm, uint6
 hipError_t launch_expand_signs(const uint64_t *bm, uint32_t words, uint64_t n, uint4 *planes,
                                hipStream_t st) {
   if (words == 0) return hipErrorInvalidValue;
-  const uint64_t total = (n + kSignPad) * words * 2;
+  const uint64_t total = (n + kSignPad) * 2;
   hipLaunchKernelGGL(k_expand_signs, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, st, bm, words, n, planes);
   return hipGetLastError();
@@ -587,7 +591,7 @@ hipError_t launch_expand_signs_ranges(const uint64_t *bm, uint32_t words, uint64
                                       const PosRange *ranges, uint32_t n_ranges, uint64_t total,
                                       uint4 *planes, hipStream_t st) {
   if (words == 0 || n_ranges == 0) return hipErrorInvalidValue;
-  const uint64_t threads = total * words * 2;
+  const uint64_t threads = total * 2;
   if (threads == 0) return hipSuccess;
   hipLaunchKernelGGL(k_expand_signs_ranges, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
                      dim3(kBlock), 0, st, bm, words, n, ranges, n_ranges, total, planes);
