@@ -165,6 +165,29 @@ def test_index_queries_match_oracle(b):
         assert sum(len(g) for g in got) > 0
 
 
+def test_index_queries_of_long_sets_match_oracle():
+    """An index over long sets (up to 2000 tokens) holds every width; query
+    batches of long sets take classes past 512 bits, whose bitmaps and sign
+    planes the query side builds only for the rows of those classes."""
+    res = _col(995, 2500, universe=40000, hi=2000, median=400.0, planted=0.2, lo=2)
+    rows = [res.set(k) for k in range(res.n_sets)]
+    batches = []
+    for k, n in enumerate((40, 300, 900)):
+        own = _col(996 + k, n, universe=40000, hi=2000, median=500.0, planted=0.1, lo=2)
+        mine = [own.set(i).tolist() for i in range(own.n_sets)]
+        # every 7th resident set, less its largest token, is queried too
+        mine += [x[:-1].tolist() for x in rows[k::7][: n // 3]]
+        batches.append(gen.from_lists(mine))
+    pq = [(1, 2), (7, 10), (4, 5)]
+    with ssj.Index(_dev(res)) as idx:
+        got, st = idx.query([_dev(x) for x in batches], [t[0] for t in pq], [t[1] for t in pq])
+        assert max(st["class_bits"][:st["n_classes"]]) >= 1024, st["class_bits"]
+        for x, (p, q), g in zip(batches, pq, got):
+            want = oracle.rs_join(x.offsets, x.tokens, res.offsets, res.tokens, p, q)
+            assert len(want) > 0
+            assert np.array_equal(g, want), (x.n_sets, p, q, len(g), len(want))
+
+
 def test_index_batch_alone_equals_batch_in_mix():
     sw = gen.served_workload(10, resident_sets=5000, max_batch=300, seed=gen.SEED_BASE + 40)
     res = sw.resident
