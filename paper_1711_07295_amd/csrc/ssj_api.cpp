@@ -52,6 +52,13 @@ constexpr uint32_t kDefaultTileCols = 2048;
 // few columns, and the launch lasts as long as its slowest tile.  (The
 // matrix-core kernel measured no gain below 64: it takes 32 columns a step.)
 constexpr uint64_t kMinSlotTiles = 16384;
+// A call of one task uses fewer, wider tiles: its blocks' column ranges are
+// long, and each tile and each size group it crosses starts with dependent
+// loads that three waves per SIMD do not hide (the 1,000,000-set join's
+// b = 128 class: 0.185 ms at 4,096 tiles against 0.246 ms at 16,384).  The
+// many short ranges of a batch's tasks balance the waves better with more
+// tiles (its b = 64 class: 1.71 ms at 16,384 against 2.18 ms at 4,096).
+constexpr uint64_t kMinSlotTilesOneTask = 4096;
 // Host threads that plan the width classes of a call's tasks (16 tasks or
 // more per thread), when the tasks' largest sizes sum to kPlanThreadSizes
 // or more.
@@ -1537,7 +1544,8 @@ void join_begin(Space &R, Space &C, const std::vector<TaskIn> &tasks, const Join
     }
     if (!jc.tile_cols_fixed) {
       const FilterShape shape = filter_shape(pl.slot_words[k], pl.slot_mfma[k]);
-      const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * kMinSlotTiles);
+      const uint64_t min_tiles = n_tasks > 1 ? kMinSlotTiles : kMinSlotTilesOneTask;
+      const uint64_t want = slot_band[k] / ((uint64_t)shape.rows * min_tiles);
       const uint32_t floor_cols = shape.mfma ? kMinTileCols : kMinTileColsValu;
       tile_cols = (uint32_t)std::max<uint64_t>(floor_cols, std::min<uint64_t>(tile_cols, want));
     }
